@@ -1,0 +1,216 @@
+"""Benchmark of the hot path: wave-LB steps with per-step surface force.
+
+Workload (one GPU): the 3D sphere, FP32 storage, 256 x 128 x 128 D3Q7,
+lambda = 256, c0 = 0.5, c_p/c0 = 1.1, R = 12, 2048 surface points, with the
+16 positions kh_j = j (pi/2)/15 run together in one handle (16 instances of
+4.19 M cells).  A step advances all 16 boxes by one time step and measures
+F(t) on every sphere.  The default K = 15360 steps is one full run (30 drive
+periods, average over the last 10) and so yields the 16 time-averaged forces.
+
+Prints one JSON line (see the keys below).  `roofline` reports the dominant
+kernel (the fused step kernel): algorithmic bytes per launch, 2 Q s bytes per
+cell update, divided by its average duration measured with HIP events on the
+handle's stream; `cpu_baseline` times the FP64 oracle on the host cores on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("wave-LB MLUPS & % HBM roofline; forces/s plain vs batched/surrogate at "
+          "≤2% error")
+HBM_PEAK_GBS = 8000.0
+SHAPE = (256, 128, 128)
+LAM, C0, CP_RATIO, RADIUS, NSURF = 256.0, 0.5, 1.1, 12.0, 2048
+N_POS = 16
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=15360)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=800)
+    return ap.parse_args()
+
+
+def problems(x_mid, k, with_surface=True):
+    import workloads
+    out = []
+    for kh in workloads.sphere_3d_positions(N_POS):
+        p = workloads.sphere_3d(x_mid, k, kh, shape=SHAPE, lam=LAM, R=RADIUS,
+                                cp_ratio=CP_RATIO, n_surf=NSURF, c0=C0)
+        if not with_surface:
+            for key in ("surf_xyz", "surf_normal", "surf_area"):
+                p.pop(key)
+        out.append(p)
+    return out
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in ("lb_kernels.hpp", "lb_wave.hip"):
+        with open(os.path.join(ROOT, "paper_2404_02346_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage):
+    """HBM bytes per step-kernel launch from the committed counter summary, if current."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_sphere16_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except OSError:
+        return None
+    if d.get("kernel_source_sha") != kernel_source_sha() or d.get("storage") != storage:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(x_mid, k, n_steps):
+    """The FP64 oracle on the host cores, one position for n_steps steps."""
+    import oracle
+    p = problems(x_mid, k)[7]
+    t0 = time.perf_counter()
+    oracle.run(p, n_steps)
+    dt = time.perf_counter() - t0
+    cells = SHAPE[0] * SHAPE[1] * SHAPE[2]
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit():
+        cores = min(cores, int(omp))
+    return {"value": cells * n_steps / dt / 1e6, "unit": "MLUPS", "cores": cores,
+            "kind": "oracle",
+            "sample": f"FP64 oracle, position kh_7 of 16, {n_steps} of 15360 steps on the full "
+                      f"256x128x128 lattice with surface measurement ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the batched instances would shard by instance; see the design notes)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2404_02346_amd as P
+    import workloads  # noqa: F401
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    omega = 2 * math.pi * C0 / LAM
+    cal = P.cavity_calibrate(SHAPE[0], C0, omega)
+    x_mid, k = cal["x_mid"], cal["k"]
+    probs = problems(x_mid, k)
+    cells = N_POS * SHAPE[0] * SHAPE[1] * SHAPE[2]
+    Q, s = 7, {"f32": 4, "f16": 2, "bf16": 2}[args.storage]
+
+    # --- whole hot path: step kernel + surface measurement, 16 instances ---
+    h = P.LBWave(probs, storage=args.storage, stream=stream)
+    tune_ms = h.autotune(6)
+    tile = h.tile()
+    h.step(args.warmup)
+    h.reset()  # the timed steps start the run from rest
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.step(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = elapsed / args.steps * 1e3
+    mlups = cells * args.steps / elapsed / 1e6
+    F, nacc = h.force(allow_empty=True)
+    full_run = args.steps >= probs[0]["n_steps"]
+    h.close()
+    del h
+
+    # --- dominant kernel alone (same instances and tile, no surface) timed with events ---
+    g = P.LBWave(problems(x_mid, k, with_surface=False), storage=args.storage, stream=stream)
+    g.set_tile(tile)
+    g.step(10)
+    n_k = min(max(args.steps // 10, 50), 1000)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    g.step(n_k)
+    e1.record(stream)
+    e1.synchronize()
+    kernel_ms = e0.elapsed_time(e1) / n_k
+    g.close()
+    del g
+    bytes_per_launch = 2 * Q * s * cells
+    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.storage)
+
+    # --- plain single-instance rate for the forces/s comparison ---
+    one = P.LBWave([probs[7]], storage=args.storage, stream=stream)
+    one.set_tile(tile)
+    one.step(10)
+    torch.cuda.synchronize()
+    n1 = 400
+    t1 = time.perf_counter()
+    one.step(n1)
+    torch.cuda.synchronize()
+    single_ms = (time.perf_counter() - t1) / n1 * 1e3
+    one.close()
+
+    n_run = probs[0]["n_steps"]
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.storage,
+        "data": "synthetic",
+        "config": {
+            "workload": "3D sphere, D3Q7 256x128x128, lambda=256, c0=0.5, c_p/c0=1.1, R=12, "
+                        "2048 Fibonacci surface points, 16 positions kh in [0, pi/2] batched "
+                        "in one handle, 30 periods (15360 steps), average over the last 10",
+            "instances": N_POS, "cells_per_step": cells, "storage": args.storage,
+            "cells_per_lane": tile, "x_antinode": round(x_mid, 4), "Pa": cal["Pa"],
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": f"step_kernel<3,{args.storage},{tile}>",
+            "kernel_ms": round(kernel_ms, 5),
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+        "forces_per_s": {
+            "batched_16": round(N_POS / (n_run * ms_per_step * 1e-3), 3),
+            "plain_single": round(1.0 / (n_run * single_ms * 1e-3), 3),
+        },
+        "autotune_ms_per_step": round(tune_ms, 4),
+    }
+    if full_run:
+        out["forces_x"] = [float(v) for v in F[:, 0]]
+        out["n_accum"] = int(nacc[0])
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(x_mid, k, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

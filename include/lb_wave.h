@@ -1,0 +1,200 @@
+/*
+ * lb_wave.h -- C ABI of the MI355X wave lattice Boltzmann library that
+ * computes the time-averaged acoustic radiation force on density-matched
+ * compressible objects.
+ *
+ * Method: Castro-Avila, Malgaretti, Harting, Munoz, "A lattice Boltzmann
+ * approach for acoustic manipulation" (arXiv 2404.02346).
+ *   - lattice, equilibrium, collision (tau = 1/2), advection:
+ *       Sec. "Lattice-Boltzmann for acoustics", eqs. MacroscopicFields,
+ *       LBM-Collision, LBM-Advection, feq_waves (D2Q5 with c_s^2 = 1/3,
+ *       D3Q7 with c_s^2 = 1/4);
+ *   - source sheet and damped walls: eqs. imposingfields, bounce-back, and
+ *       the set-up of Sec. "Results and discussion" (absorbing wall x = 0,
+ *       source x = 1, reflector x = Lx-1, periodic y and z);
+ *   - object: per-cell sound speed of eq. sound_speed_object, read with
+ *       c = c_p inside and c = c0 outside;
+ *   - measurement: kernel interpolation (eq. InterpolatedFields, 3-point
+ *       kernel applied as a tensor product) onto surface elements, surface
+ *       integral eq. arf_integral_LBM at every step, time average over the
+ *       steps t >= avg_start.
+ *
+ * Conventions
+ *   - All functions have C linkage and return an lb_status (0 = success,
+ *     negative = error) unless stated otherwise; lb_last_error() gives a
+ *     thread-local message for the last failure.
+ *   - Pointers are HOST pointers unless the name starts with dev_.
+ *   - Lattice units: dx = dt = 1.  Node (x, y, z) sits at integer
+ *     coordinates 0 <= x < nx etc.; cell index (z*ny + y)*nx + x.
+ *   - Velocity order 0, +x, -x, +y, -y, +z, -z (Q = 5 in 2D, 7 in 3D).
+ *   - A "state" is f^new, the post-collision populations before advection,
+ *     which is the instant the paper reads results at.  Step t advects the
+ *     state of step t-1, collides, applies the sheets and measures F(t)
+ *     from rho1, J1 of the advected populations.
+ *   - The library never allocates device memory: the caller passes one
+ *     device workspace (e.g. a torch uint8 tensor) of at least
+ *     lb_wave_workspace_bytes() bytes, 256-byte aligned, which it owns and
+ *     must keep alive until lb_wave_destroy().  Work is enqueued on the
+ *     caller's HIP stream.
+ *   - A handle is not thread-safe; calls on one handle must not overlap.
+ */
+#ifndef LB_WAVE_H
+#define LB_WAVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Storage precision of the populations.  F64 and F32 compute in their own
+ * precision; F16 and BF16 store 16-bit values (times a power-of-two scale)
+ * and compute the collision in FP32.  Interpolation and the surface integral
+ * are FP64 in every mode; the time accumulator is FP64. */
+typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F16 = 2, LB_BF16 = 3 } lb_storage;
+
+/* Boundary along x: the paper's driven sheets, or periodic (no sheets). */
+typedef enum { LB_XBC_DRIVEN = 0, LB_XBC_PERIODIC = 1 } lb_xbc;
+
+typedef enum {
+    LB_OK = 0,
+    LB_EINVAL = -1,      /* bad argument, shape or parameter */
+    LB_ENOMEM = -2,      /* workspace too small or misaligned */
+    LB_EUNSTABLE = -3,   /* some c(x) > 1/sqrt(dim): the tau = 1/2 scheme grows */
+    LB_EGEOMETRY = -4,   /* a surface stencil touches an x sheet or leaves the box */
+    LB_EDEVICE = -5,     /* a HIP call failed */
+    LB_ENAN = -6,        /* a measured force was not finite */
+    LB_EEMPTY = -7       /* no step has been accumulated yet */
+} lb_status;
+
+/* One problem instance (one box with one object). */
+typedef struct lb_wave_desc {
+    int32_t dim;                /* 2 (D2Q5) or 3 (D3Q7) */
+    int32_t nx, ny, nz;         /* lattice size; nz = 1 when dim = 2 */
+    int32_t storage;            /* lb_storage; identical for all instances of a handle */
+    int32_t xbc;                /* lb_xbc */
+    double c0, rho0;            /* fluid sound speed (cells/step) and mean density */
+    const double *c_field;      /* optional nx*ny*nz per-cell sound speed (cell index
+                                   order); NULL selects the analytic object below */
+    double obj_center[3];       /* object centre r0 (z ignored in 2D) */
+    double obj_radius;          /* R_p */
+    double obj_cp;              /* sound speed inside the object c_p */
+    double obj_d;               /* "square thickness" d of the tanh profile (paper: 4) */
+    double rho_a;               /* source amplitude: rho1(x = 1) = rho_a sin(omega t) */
+    double omega;               /* drive angular frequency (rad/step) */
+    double wall_phi;            /* bounce-back damping Phi in [0, 1) (paper: 0.99) */
+    int32_t n_surf;             /* number of surface elements N (may be 0) */
+    const double *surf_xyz;     /* N*3 element centres R_k */
+    const double *surf_normal;  /* N*3 outward unit normals n_k */
+    const double *surf_area;    /* N element sizes dS_k (length in 2D, area in 3D) */
+    int64_t avg_start;          /* F(t) enters the average for t >= avg_start */
+    int64_t max_steps;          /* the instance freezes after this many steps; <= 0: never */
+    int64_t trace_steps;        /* keep F(t) for t < trace_steps (0: no trace) */
+} lb_wave_desc;
+
+typedef struct lb_wave lb_wave;  /* opaque handle */
+
+/* Check descriptors on the host only (no device call).  Returns LB_OK or the
+ * first error: LB_EINVAL (shapes, dim, storage mismatch between instances,
+ * missing surface arrays, rho0 <= 0, wall_phi outside [0, 1), nx < 3 with
+ * driven x), LB_EUNSTABLE (c0, c_p or any c_field value above 1/sqrt(dim),
+ * the stability bound of the tau = 1/2 scheme), LB_EGEOMETRY (a 3-point
+ * stencil reaches x < 2 or x > nx-2 in driven mode, where the sheets change
+ * the moments, or leaves 0 <= x < nx in periodic mode). */
+int lb_wave_check(const lb_wave_desc *descs, int32_t n_inst);
+
+/* Device bytes needed for n_inst instances (0 if lb_wave_check fails). */
+size_t lb_wave_workspace_bytes(const lb_wave_desc *descs, int32_t n_inst);
+
+/* Create a handle: validates, copies every host array (the caller may free
+ * them on return), lays out the workspace, builds the compact c^2 tables
+ * and surface stencils, and zeroes the state (f^new of step -1 = 0) and the
+ * accumulators, all on `hip_stream` (hipStream_t, NULL = default stream).
+ * dev_workspace must be 256-byte aligned device memory of workspace_bytes
+ * >= lb_wave_workspace_bytes().  On success *out receives the handle. */
+int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspace,
+                   size_t workspace_bytes, void *hip_stream, lb_wave **out);
+
+/* Enqueue n_steps steps for every instance (an instance past max_steps is
+ * left untouched).  Asynchronous: returns after enqueueing.  Returns LB_ENAN
+ * if a previous lb_surface_force() found a non-finite force. */
+int lb_wave_step_n(lb_wave *h, int64_t n_steps);
+
+/* Synchronise the stream and return, per instance in the order given to
+ * create, the time average of F(t) over the accumulated steps
+ * (F_avg: n_inst*3 doubles, required) and the number of accumulated steps
+ * (n_accum: n_inst, may be NULL).  LB_EEMPTY if some instance has none
+ * (its F_avg is then 0), LB_ENAN if some force was not finite. */
+int lb_surface_force(lb_wave *h, double *F_avg, int64_t *n_accum);
+
+/* Release the handle (NULL-safe).  Does not free the caller's workspace. */
+int lb_wave_destroy(lb_wave *h);
+
+/* Thread-local message of the last failure ("" if none). */
+const char *lb_last_error(void);
+
+/* ---- inspection and control (tests, benchmarks) ---- */
+
+/* Steps enqueued so far (global step counter t). */
+int lb_wave_steps_done(const lb_wave *h, int64_t *t);
+
+/* Zero the state, the step counter and the accumulators (stream-ordered). */
+int lb_wave_reset(lb_wave *h);
+
+/* Copy the current state of instance `inst` to/from the host as FP64
+ * cells x Q (array-of-structures, cell index order, unscaled).  Both
+ * synchronise the stream.  set_state replaces the state the next step
+ * advects (f^new of the previous step); 16-bit storage rounds it. */
+int lb_wave_get_state(lb_wave *h, int32_t inst, double *host_fnew);
+int lb_wave_set_state(lb_wave *h, int32_t inst, const double *host_fnew);
+
+/* Copy F(t) for t = 0 .. n-1 (n <= trace_steps) of instance `inst` to
+ * host (n*3 doubles); synchronises the stream. */
+int lb_wave_force_trace(lb_wave *h, int32_t inst, double *host_F, int64_t n);
+
+/* Where the populations live inside the workspace (for zero-copy reads):
+ * offset in bytes of population plane 0 of the current state buffer,
+ * bytes between planes, elements per row (pitch >= nx) and the storage
+ * scale s (stored value = s * f). */
+typedef struct lb_state_view {
+    size_t offset_bytes;
+    size_t plane_bytes;
+    int32_t pitch;
+    int32_t elem_bytes;
+    double scale;
+} lb_state_view;
+int lb_wave_state_view(const lb_wave *h, int32_t inst, lb_state_view *v);
+
+/* Tile shape of the step kernel: cells per lane along x (1, 2 or 4).
+ * lb_wave_autotune times every shape for n_trial steps on the handle's own
+ * instances, keeps the fastest, then resets the state (lb_wave_reset).
+ * best_ms (may be NULL) receives the winning time per step in ms. */
+int lb_wave_set_tile(lb_wave *h, int32_t cells_per_lane);
+int lb_wave_get_tile(const lb_wave *h, int32_t *cells_per_lane);
+int lb_wave_autotune(lb_wave *h, int32_t n_trial, double *best_ms);
+
+/* ---- empty-cavity calibration of the driven standing wave ---- */
+
+/* Runs the empty driven box (x sheets as above, no object; the field
+ * depends on x only, so it is the three-population 1D lattice with rest
+ * weight 1 - c0^2) for n_periods drive periods on the GPU, takes the
+ * complex amplitude P(x) of rho1 at omega over the last n_fit periods, fits
+ * |P|^2 = a + b cos 2kx + c sin 2kx with k the lattice wavenumber
+ * (cos omega = 1 - c0^2 (1 - cos k)) and returns
+ *   out[0] = A    = sqrt(a + sqrt(b^2 + c^2))  (rho1 amplitude at an antinode)
+ *   out[1] = x_a  = the antinode closest to (nx-1)/2 from below
+ *   out[2] = k
+ *   out[3..5] = a, b, c
+ * and, if host_P is not NULL, Re P(x), Im P(x) interleaved (2*nx doubles).
+ * Needs lb_cavity_workspace_bytes(nx) bytes of device workspace; 16 <= nx <= 2048.
+ * Synchronises the stream. */
+size_t lb_cavity_workspace_bytes(int32_t nx);
+int lb_cavity_calibrate(int32_t nx, double c0, double omega, double rho_a, double wall_phi,
+                        int32_t n_periods, int32_t n_fit, void *dev_workspace,
+                        size_t workspace_bytes, void *hip_stream, double *out, double *host_P);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LB_WAVE_H */

@@ -1,0 +1,988 @@
+// Host side of the wave lattice Boltzmann library: the C ABI declared in
+// include/lb_wave.h (descriptor checks, workspace layout, compact sound-speed
+// tables, surface stencils, launches and read-back).
+//
+// Method: Castro-Avila et al., "A lattice Boltzmann approach for acoustic
+// manipulation" (arXiv 2404.02346).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/lb_wave.h"
+#include "lb_kernels.hpp"
+
+using namespace lbw;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                    \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(LB_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+
+size_t elem_bytes(int storage)
+{
+    switch (storage) {
+    case LB_F64: return 8;
+    case LB_F32: return 4;
+    default: return 2;
+    }
+}
+size_t compute_bytes(int storage) { return storage == LB_F64 ? 8 : 4; }
+
+inline int wrapi(long v, int n)
+{
+    long r = v % n;
+    return (int)(r < 0 ? r + n : r);
+}
+
+// The 3-point kernel printed after eq. InterpolatedFields.
+double roma3(double r)
+{
+    const double a = std::fabs(r);
+    if (a <= 0.5) return (1.0 + std::sqrt(1.0 - 3.0 * a * a)) / 3.0;
+    if (a <= 1.5) return (5.0 - 3.0 * a - std::sqrt(1.0 - 3.0 * (1.0 - a) * (1.0 - a))) / 6.0;
+    return 0.0;
+}
+
+// Sound speed of eq. sound_speed_object, read with c = c_p inside.  For
+// (r^2 - R^2)/d >= 20 the tanh rounds to 1 and c is exactly c0.
+double object_c(const lb_wave_desc &d, double x, double y, double z)
+{
+    const double dx = x - d.obj_center[0], dy = y - d.obj_center[1];
+    const double dz = d.dim == 3 ? z - d.obj_center[2] : 0.0;
+    const double u = (dx * dx + dy * dy + dz * dz - d.obj_radius * d.obj_radius) / d.obj_d;
+    return d.c0 - 0.5 * (d.c0 - d.obj_cp) * (1.0 - std::tanh(u));
+}
+
+constexpr double kTanhSaturate = 20.0;
+
+inline bool finite(double v) { return std::isfinite(v); }
+
+// Box of cells whose sound speed differs from c0 (inclusive lo, extent n).
+struct Box {
+    int lo[3] = {0, 0, 0};
+    int n[3] = {0, 0, 0};
+    size_t cells() const { return (size_t)n[0] * n[1] * n[2]; }
+};
+
+Box sound_speed_box(const lb_wave_desc &d)
+{
+    Box b;
+    const int nn[3] = {d.nx, d.ny, d.dim == 3 ? d.nz : 1};
+    if (d.c_field) {
+        int lo[3] = {nn[0], nn[1], nn[2]}, hi[3] = {-1, -1, -1};
+        for (int z = 0; z < nn[2]; ++z)
+            for (int y = 0; y < nn[1]; ++y)
+                for (int x = 0; x < nn[0]; ++x) {
+                    const double c = d.c_field[((size_t)z * nn[1] + y) * nn[0] + x];
+                    if (c != d.c0) {
+                        const int p[3] = {x, y, z};
+                        for (int a = 0; a < 3; ++a) {
+                            lo[a] = std::min(lo[a], p[a]);
+                            hi[a] = std::max(hi[a], p[a]);
+                        }
+                    }
+                }
+        if (hi[0] < 0) return b;
+        for (int a = 0; a < 3; ++a) {
+            b.lo[a] = lo[a];
+            b.n[a] = hi[a] - lo[a] + 1;
+        }
+        return b;
+    }
+    if (d.obj_cp == d.c0) return b;  // c = c0 exactly everywhere
+    const double h = std::sqrt(d.obj_radius * d.obj_radius + kTanhSaturate * d.obj_d);
+    for (int a = 0; a < 3; ++a) {
+        if (a == 2 && d.dim == 2) {
+            b.lo[2] = 0;
+            b.n[2] = 1;
+            continue;
+        }
+        long lo = (long)std::floor(d.obj_center[a] - h);
+        long hi = (long)std::ceil(d.obj_center[a] + h);
+        lo = std::max(lo, 0L);
+        hi = std::min(hi, (long)nn[a] - 1);
+        if (hi < lo) return Box{};
+        b.lo[a] = (int)lo;
+        b.n[a] = (int)(hi - lo + 1);
+    }
+    return b;
+}
+
+// 3-point stencil of one surface point: base node by rounding half away from
+// zero, nodes base-1, base, base+1 along each axis.
+void stencil(const lb_wave_desc &d, const double *P, SurfPt &s, long xn[3])
+{
+    const int nn[3] = {d.nx, d.ny, d.dim == 3 ? d.nz : 1};
+    for (int a = 0; a < 3; ++a) {
+        if (a == 2 && d.dim == 2) {
+            for (int o = 0; o < 3; ++o) {
+                s.iz[o] = 0;
+                s.w[6 + o] = (o == 0) ? 1.0 : 0.0;
+            }
+            continue;
+        }
+        const long b = std::lround(P[a]);
+        for (int o = 0; o < 3; ++o) {
+            const long node = b - 1 + o;
+            const double w = roma3((double)node - P[a]);
+            if (a == 0) {
+                xn[o] = node;
+                s.ix[o] = (int)node;
+                s.w[o] = w;
+            } else if (a == 1) {
+                s.iy[o] = wrapi(node, nn[1]);
+                s.w[3 + o] = w;
+            } else {
+                s.iz[o] = wrapi(node, nn[2]);
+                s.w[6 + o] = w;
+            }
+        }
+    }
+    s.pad = 0;
+}
+
+int check_one(const lb_wave_desc &d, const lb_wave_desc &d0, int idx)
+{
+    if (d.dim != 2 && d.dim != 3) return fail(LB_EINVAL, "instance %d: dim must be 2 or 3", idx);
+    if (d.dim != d0.dim) return fail(LB_EINVAL, "instance %d: all instances must share dim", idx);
+    if (d.nx < 1 || d.ny < 1 || d.nz < 1) return fail(LB_EINVAL, "instance %d: bad shape", idx);
+    if (d.dim == 2 && d.nz != 1) return fail(LB_EINVAL, "instance %d: nz must be 1 in 2D", idx);
+    if (d.storage < LB_F64 || d.storage > LB_BF16)
+        return fail(LB_EINVAL, "instance %d: bad storage", idx);
+    if (d.storage != d0.storage)
+        return fail(LB_EINVAL, "instance %d: all instances must share storage", idx);
+    if (d.xbc != LB_XBC_DRIVEN && d.xbc != LB_XBC_PERIODIC)
+        return fail(LB_EINVAL, "instance %d: bad xbc", idx);
+    if (d.xbc == LB_XBC_DRIVEN && d.nx < 3)
+        return fail(LB_EINVAL, "instance %d: driven x needs nx >= 3", idx);
+    if (!(d.c0 > 0) || !finite(d.c0)) return fail(LB_EINVAL, "instance %d: c0 must be > 0", idx);
+    if (!(d.rho0 > 0) || !finite(d.rho0))
+        return fail(LB_EINVAL, "instance %d: rho0 must be > 0", idx);
+    if (!(d.wall_phi >= 0 && d.wall_phi < 1))
+        return fail(LB_EINVAL, "instance %d: wall_phi must lie in [0, 1)", idx);
+    if (!finite(d.rho_a) || !finite(d.omega))
+        return fail(LB_EINVAL, "instance %d: rho_a and omega must be finite", idx);
+    if (d.avg_start < 0 || d.trace_steps < 0)
+        return fail(LB_EINVAL, "instance %d: avg_start and trace_steps must be >= 0", idx);
+    // sizes: rows and wave tasks are indexed with 32-bit integers
+    const long pitch = (long)align_up((size_t)d.nx, 64);
+    const long rows = (long)d.ny * d.nz;
+    if (pitch * rows > (long)INT32_MAX * 8 || rows * ((pitch + 63) / 64) > INT32_MAX / 2)
+        return fail(LB_EINVAL, "instance %d: lattice too large", idx);
+    // stability of the tau = 1/2 scheme: every c <= 1/sqrt(dim)
+    const double cmax_allowed = 1.0 / std::sqrt((double)d.dim) * (1.0 + 1e-12);
+    double cmax = d.c0;
+    if (d.c_field) {
+        const size_t n = (size_t)d.nx * d.ny * d.nz;
+        for (size_t i = 0; i < n; ++i) {
+            if (!finite(d.c_field[i])) return fail(LB_EINVAL, "instance %d: c_field not finite", idx);
+            cmax = std::max(cmax, std::fabs(d.c_field[i]));
+        }
+    } else {
+        if (!finite(d.obj_cp) || !finite(d.obj_radius) || !finite(d.obj_d) ||
+            !finite(d.obj_center[0]) || !finite(d.obj_center[1]) || !finite(d.obj_center[2]))
+            return fail(LB_EINVAL, "instance %d: object parameters not finite", idx);
+        if (d.obj_cp != d.c0 && !(d.obj_d > 0))
+            return fail(LB_EINVAL, "instance %d: obj_d must be > 0", idx);
+        cmax = std::max(cmax, std::fabs(d.obj_cp));
+    }
+    if (cmax > cmax_allowed)
+        return fail(LB_EUNSTABLE, "instance %d: sound speed %.6g exceeds 1/sqrt(%d)", idx, cmax,
+                    d.dim);
+    if (d.n_surf < 0) return fail(LB_EINVAL, "instance %d: n_surf < 0", idx);
+    if (d.n_surf > 0) {
+        if (!d.surf_xyz || !d.surf_normal || !d.surf_area)
+            return fail(LB_EINVAL, "instance %d: surface arrays missing", idx);
+        const long xlo = d.xbc == LB_XBC_DRIVEN ? 2 : 0;
+        const long xhi = d.xbc == LB_XBC_DRIVEN ? d.nx - 2 : d.nx - 1;
+        for (int k = 0; k < d.n_surf; ++k) {
+            for (int a = 0; a < 3; ++a)
+                if (!finite(d.surf_xyz[3 * k + a]) || !finite(d.surf_normal[3 * k + a]))
+                    return fail(LB_EINVAL, "instance %d: surface point %d not finite", idx, k);
+            if (!finite(d.surf_area[k]))
+                return fail(LB_EINVAL, "instance %d: surface area %d not finite", idx, k);
+            SurfPt s;
+            long xn[3];
+            stencil(d, d.surf_xyz + 3 * k, s, xn);
+            if (xn[0] < xlo || xn[2] > xhi)
+                return fail(LB_EGEOMETRY,
+                            "instance %d: stencil of surface point %d spans x = %ld..%ld, "
+                            "outside %ld..%ld",
+                            idx, k, xn[0], xn[2], xlo, xhi);
+        }
+    }
+    return LB_OK;
+}
+
+int check_all(const lb_wave_desc *descs, int n)
+{
+    if (!descs || n < 1) return fail(LB_EINVAL, "need at least one descriptor");
+    long tasks = 0;
+    for (int i = 0; i < n; ++i) {
+        int st = check_one(descs[i], descs[0], i);
+        if (st != LB_OK) return st;
+        const long xsegs = (descs[i].nx + 63) / 64;
+        tasks += xsegs * descs[i].ny * descs[i].nz;
+        if (tasks > INT32_MAX / 2) return fail(LB_EINVAL, "batch too large");
+    }
+    return LB_OK;
+}
+
+struct InstPlan {
+    Box box;
+    int pitch;
+    int64_t plane;
+    size_t off_surf, off_contrib, off_trace, off_box, off_buf[2];
+};
+
+struct Layout {
+    size_t off_inst, off_acc, total;
+    std::vector<InstPlan> p;
+};
+
+Layout plan(const lb_wave_desc *descs, int n)
+{
+    Layout L;
+    size_t off = 0;
+    L.off_inst = off;
+    off = align_up(off + sizeof(InstDev) * n);
+    L.off_acc = off;
+    off = align_up(off + sizeof(AccDev) * n);
+    L.p.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const lb_wave_desc &d = descs[i];
+        InstPlan &P = L.p[i];
+        const int Q = 2 * d.dim + 1;
+        P.box = sound_speed_box(d);
+        P.pitch = (int)align_up((size_t)d.nx, 64);
+        P.plane = (int64_t)P.pitch * d.ny * d.nz;
+        P.off_surf = off;
+        off = align_up(off + sizeof(SurfPt) * d.n_surf);
+        P.off_contrib = off;
+        off = align_up(off + sizeof(double) * 4 * d.n_surf);
+        P.off_trace = off;
+        off = align_up(off + sizeof(double) * 3 * (size_t)d.trace_steps);
+        P.off_box = off;
+        off = align_up(off + compute_bytes(d.storage) * P.box.cells());
+        for (int b = 0; b < 2; ++b) {
+            P.off_buf[b] = off;
+            off = align_up(off + elem_bytes(d.storage) * (size_t)P.plane * Q);
+        }
+    }
+    L.total = off;
+    return L;
+}
+
+double storage_scale(const lb_wave_desc &d)
+{
+    if (d.storage == LB_F64 || d.storage == LB_F32) return 1.0;
+    if (!(std::fabs(d.rho_a) > 0)) return 1.0;
+    return std::ldexp(1.0, (int)std::lround(-std::log2(std::fabs(d.rho_a))));
+}
+
+// ---- host conversions for state read-back ----
+inline float bf16_to_f(uint16_t b)
+{
+    uint32_t u = (uint32_t)b << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+inline uint16_t f_to_bf16(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+inline double load_host(const uint8_t *p, int storage)
+{
+    switch (storage) {
+    case LB_F64: { double v; std::memcpy(&v, p, 8); return v; }
+    case LB_F32: { float v; std::memcpy(&v, p, 4); return v; }
+    case LB_F16: { _Float16 v; std::memcpy(&v, p, 2); return (double)(float)v; }
+    default: { uint16_t v; std::memcpy(&v, p, 2); return (double)bf16_to_f(v); }
+    }
+}
+inline void store_host(uint8_t *p, int storage, double v)
+{
+    switch (storage) {
+    case LB_F64: std::memcpy(p, &v, 8); break;
+    case LB_F32: { float f = (float)v; std::memcpy(p, &f, 4); break; }
+    case LB_F16: { _Float16 h = (_Float16)(float)v; std::memcpy(p, &h, 2); break; }
+    default: { uint16_t b = f_to_bf16((float)v); std::memcpy(p, &b, 2); break; }
+    }
+}
+
+}  // namespace
+
+struct lb_wave {
+    int n = 0, dim = 0, storage = 0, vx = 1;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    Layout lay;
+    std::vector<lb_wave_desc> desc;   // user order (host arrays not kept)
+    std::vector<int> order;           // internal -> user
+    std::vector<int> pos;             // user -> internal
+    std::vector<InstDev> hinst;       // internal order
+    std::vector<int> task0;           // internal order, size n + 1
+    std::vector<SegInfo> segs;        // runs of equal shape, internal order
+    std::vector<double> scale;        // user order
+    InstDev *d_inst = nullptr;
+    AccDev *d_acc = nullptr;          // internal order
+    int max_surf = 0;
+    bool any_surf = false;
+    int64_t t = 0;
+    bool nan_seen = false;
+};
+
+namespace {
+
+int64_t steps_of(const lb_wave *h, int internal)
+{
+    const int64_t ms = h->hinst[internal].max_steps;
+    return ms > 0 ? std::min(h->t, ms) : h->t;
+}
+
+int active_prefix(const lb_wave *h, int64_t t)
+{
+    int n = 0;
+    while (n < h->n) {
+        const int64_t ms = h->hinst[n].max_steps;
+        if (ms > 0 && t >= ms) break;
+        ++n;
+    }
+    return n;
+}
+
+template <int DIM, typename S, int VX>
+void launch_step_t(const StepArgs &a, hipStream_t st)
+{
+    const int blocks = (a.ntask + 3) / 4;
+    hipLaunchKernelGGL((step_kernel<DIM, S, VX>), dim3(blocks), dim3(kStepThreads), 0, st, a);
+}
+
+template <int DIM, typename S>
+void launch_step_s(const StepArgs &a, int vx, hipStream_t st)
+{
+    switch (vx) {
+    case 2: launch_step_t<DIM, S, 2>(a, st); break;
+    case 4: launch_step_t<DIM, S, 4>(a, st); break;
+    default: launch_step_t<DIM, S, 1>(a, st); break;
+    }
+}
+
+template <int DIM>
+void launch_step_d(const StepArgs &a, int storage, int vx, hipStream_t st)
+{
+    switch (storage) {
+    case LB_F64: launch_step_s<DIM, double>(a, vx, st); break;
+    case LB_F32: launch_step_s<DIM, float>(a, vx, st); break;
+    case LB_F16: launch_step_s<DIM, _Float16>(a, vx, st); break;
+    default: launch_step_s<DIM, bf16>(a, vx, st); break;
+    }
+}
+
+template <int DIM>
+void launch_surface_d(const lb_wave *h, int64_t t, int n_active)
+{
+    const dim3 g((h->max_surf + 63) / 64, n_active);
+    const int thr = 64 * (DIM == 3 ? 3 : 1);
+    switch (h->storage) {
+    case LB_F64:
+        hipLaunchKernelGGL((surface_interp_kernel<DIM, double>), g, dim3(thr), 0, h->stream,
+                           h->d_inst, t, 0);
+        break;
+    case LB_F32:
+        hipLaunchKernelGGL((surface_interp_kernel<DIM, float>), g, dim3(thr), 0, h->stream,
+                           h->d_inst, t, 0);
+        break;
+    case LB_F16:
+        hipLaunchKernelGGL((surface_interp_kernel<DIM, _Float16>), g, dim3(thr), 0, h->stream,
+                           h->d_inst, t, 0);
+        break;
+    default:
+        hipLaunchKernelGGL((surface_interp_kernel<DIM, bf16>), g, dim3(thr), 0, h->stream,
+                           h->d_inst, t, 0);
+        break;
+    }
+    hipLaunchKernelGGL(surface_reduce_kernel, dim3(n_active), dim3(256), 0, h->stream,
+                       h->d_inst, t, 0);
+}
+
+// One step for every active instance: fused step kernel(s), then the
+// surface measurement of the state it wrote.
+int enqueue_step(lb_wave *h)
+{
+    const int64_t t = h->t;
+    const int na = active_prefix(h, t);
+    if (na == 0) {
+        h->t++;
+        return LB_OK;
+    }
+    const int ntask_active = h->task0[na];
+    size_t s = 0;
+    while (s < h->segs.size() && h->segs[s].task0 < ntask_active) {
+        StepArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.inst = h->d_inst;
+        a.t = t;
+        const int base = h->segs[s].task0;
+        int k = 0;
+        for (; k < kMaxSeg && s + k < h->segs.size() && h->segs[s + k].task0 < ntask_active; ++k) {
+            a.seg[k] = h->segs[s + k];
+            a.seg[k].task0 -= base;
+        }
+        const int end = (s + k < h->segs.size()) ? std::min(h->segs[s + k].task0, ntask_active)
+                                                 : ntask_active;
+        a.nseg = k;
+        a.ntask = end - base;
+        if (h->dim == 2)
+            launch_step_d<2>(a, h->storage, h->vx, h->stream);
+        else
+            launch_step_d<3>(a, h->storage, h->vx, h->stream);
+        s += k;
+    }
+    if (h->any_surf) {
+        if (h->dim == 2)
+            launch_surface_d<2>(h, t, na);
+        else
+            launch_surface_d<3>(h, t, na);
+    }
+    HIP_TRY(hipGetLastError());
+    h->t++;
+    return LB_OK;
+}
+
+int zero_region(lb_wave *h, size_t off, size_t bytes)
+{
+    if (bytes == 0) return LB_OK;
+    const int64_t n16 = (int64_t)((bytes + 15) / 16);
+    const int blocks = (int)std::min<int64_t>((n16 + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, h->stream,
+                       reinterpret_cast<uint4 *>(h->ws + off), n16);
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+int zero_state(lb_wave *h)
+{
+    for (int i = 0; i < h->n; ++i) {
+        const InstPlan &P = h->lay.p[i];
+        const lb_wave_desc &d = h->desc[i];
+        const size_t buf = elem_bytes(d.storage) * (size_t)P.plane * (2 * d.dim + 1);
+        for (int b = 0; b < 2; ++b) {
+            int st = zero_region(h, P.off_buf[b], buf);
+            if (st) return st;
+        }
+        int st = zero_region(h, P.off_trace, sizeof(double) * 3 * (size_t)d.trace_steps);
+        if (st) return st;
+    }
+    int st = zero_region(h, h->lay.off_acc, sizeof(AccDev) * h->n);
+    if (st) return st;
+    h->t = 0;
+    h->nan_seen = false;
+    return LB_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *lb_last_error(void) { return g_err.c_str(); }
+
+int lb_wave_check(const lb_wave_desc *descs, int32_t n_inst)
+{
+    g_err.clear();
+    return check_all(descs, n_inst);
+}
+
+size_t lb_wave_workspace_bytes(const lb_wave_desc *descs, int32_t n_inst)
+{
+    if (check_all(descs, n_inst) != LB_OK) return 0;
+    return plan(descs, n_inst).total;
+}
+
+int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspace,
+                   size_t workspace_bytes, void *hip_stream, lb_wave **out)
+{
+    g_err.clear();
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    int st = check_all(descs, n_inst);
+    if (st != LB_OK) return st;
+    Layout L = plan(descs, n_inst);
+    if (!dev_workspace) return fail(LB_ENOMEM, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(dev_workspace) % kAlign)
+        return fail(LB_ENOMEM, "workspace must be 256-byte aligned");
+    if (workspace_bytes < L.total)
+        return fail(LB_ENOMEM, "workspace has %zu bytes, needs %zu", workspace_bytes, L.total);
+
+    lb_wave *h = new lb_wave();
+    h->n = n_inst;
+    h->dim = descs[0].dim;
+    h->storage = descs[0].storage;
+    h->ws = static_cast<char *>(dev_workspace);
+    h->ws_bytes = workspace_bytes;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->lay = L;
+    h->desc.assign(descs, descs + n_inst);
+    for (auto &d : h->desc) {  // the host arrays are not kept
+        d.c_field = nullptr;
+        d.surf_xyz = d.surf_normal = d.surf_area = nullptr;
+    }
+    h->d_inst = reinterpret_cast<InstDev *>(h->ws + L.off_inst);
+    h->d_acc = reinterpret_cast<AccDev *>(h->ws + L.off_acc);
+    h->vx = 1;
+
+    // internal order: longest runs first (so the active set is a prefix),
+    // equal shapes adjacent (so they share one segment of the launch)
+    h->order.resize(n_inst);
+    std::iota(h->order.begin(), h->order.end(), 0);
+    auto key_steps = [&](int i) {
+        return descs[i].max_steps > 0 ? descs[i].max_steps : std::numeric_limits<int64_t>::max();
+    };
+    std::stable_sort(h->order.begin(), h->order.end(), [&](int a, int b) {
+        if (key_steps(a) != key_steps(b)) return key_steps(a) > key_steps(b);
+        if (descs[a].nx != descs[b].nx) return descs[a].nx > descs[b].nx;
+        if (descs[a].ny != descs[b].ny) return descs[a].ny > descs[b].ny;
+        return descs[a].nz > descs[b].nz;
+    });
+    h->pos.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) h->pos[h->order[i]] = i;
+
+    // per-instance device records, surface stencils, sound-speed boxes
+    std::vector<std::vector<uint8_t>> host_blobs;
+    std::vector<size_t> blob_off;
+    h->hinst.resize(n_inst);
+    h->scale.resize(n_inst);
+    h->task0.assign(n_inst + 1, 0);
+    for (int ii = 0; ii < n_inst; ++ii) {
+        const int u = h->order[ii];
+        const lb_wave_desc &d = descs[u];
+        const InstPlan &P = L.p[u];
+        InstDev &I = h->hinst[ii];
+        std::memset(&I, 0, sizeof I);
+        I.dim = d.dim;
+        I.nx = d.nx;
+        I.ny = d.ny;
+        I.nz = d.nz;
+        I.pitch = P.pitch;
+        I.xbc = d.xbc;
+        I.plane = P.plane;
+        I.buf[0] = h->ws + P.off_buf[0];
+        I.buf[1] = h->ws + P.off_buf[1];
+        I.c0sq = d.c0 * d.c0;
+        for (int a = 0; a < 3; ++a) {
+            I.bb_lo[a] = P.box.lo[a];
+            I.bb_n[a] = P.box.n[a];
+        }
+        I.c2box = h->ws + P.off_box;
+        const double sc = storage_scale(d);
+        h->scale[u] = sc;
+        I.src_amp = d.rho_a * sc;
+        I.omega = d.omega;
+        I.wall_phi = d.wall_phi;
+        I.max_steps = d.max_steps;
+        I.n_surf = d.n_surf;
+        I.surf = reinterpret_cast<const SurfPt *>(h->ws + P.off_surf);
+        I.contrib = reinterpret_cast<double *>(h->ws + P.off_contrib);
+        I.c0sq_force = d.c0 * d.c0;
+        I.force_scale = -1.0 / (d.rho0 * sc * sc);
+        I.avg_start = d.avg_start;
+        I.acc = h->d_acc + ii;
+        I.trace = reinterpret_cast<double *>(h->ws + P.off_trace);
+        I.trace_cap = d.trace_steps;
+        h->max_surf = std::max(h->max_surf, d.n_surf);
+        if (d.n_surf > 0) h->any_surf = true;
+
+        const int xsegs = (d.nx + 63) / 64;
+        h->task0[ii + 1] = h->task0[ii] + xsegs * d.ny * d.nz;
+
+        // surface stencils
+        if (d.n_surf > 0) {
+            std::vector<uint8_t> blob(sizeof(SurfPt) * d.n_surf);
+            SurfPt *sp = reinterpret_cast<SurfPt *>(blob.data());
+            for (int k = 0; k < d.n_surf; ++k) {
+                long xn[3];
+                stencil(d, d.surf_xyz + 3 * k, sp[k], xn);
+                for (int a = 0; a < 3; ++a) sp[k].nA[a] = d.surf_normal[3 * k + a] * d.surf_area[k];
+            }
+            host_blobs.push_back(std::move(blob));
+            blob_off.push_back(P.off_surf);
+        }
+        // compact c^2 table in the compute type
+        if (P.box.cells() > 0) {
+            const size_t cb = compute_bytes(d.storage);
+            std::vector<uint8_t> blob(cb * P.box.cells());
+            size_t q = 0;
+            for (int z = 0; z < P.box.n[2]; ++z)
+                for (int y = 0; y < P.box.n[1]; ++y)
+                    for (int x = 0; x < P.box.n[0]; ++x, ++q) {
+                        const int gx = P.box.lo[0] + x, gy = P.box.lo[1] + y, gz = P.box.lo[2] + z;
+                        double c;
+                        if (d.c_field)
+                            c = d.c_field[((size_t)gz * d.ny + gy) * d.nx + gx];
+                        else
+                            c = object_c(d, gx, gy, gz);
+                        const double c2 = c * c;
+                        if (cb == 8) {
+                            std::memcpy(blob.data() + 8 * q, &c2, 8);
+                        } else {
+                            const float f = (float)c2;
+                            std::memcpy(blob.data() + 4 * q, &f, 4);
+                        }
+                    }
+            host_blobs.push_back(std::move(blob));
+            blob_off.push_back(P.off_box);
+        }
+    }
+    // segments: maximal runs of equal shape in internal order
+    for (int ii = 0; ii < n_inst; ++ii) {
+        const InstDev &I = h->hinst[ii];
+        if (ii == 0 || I.nx != h->hinst[ii - 1].nx || I.ny != h->hinst[ii - 1].ny ||
+            I.nz != h->hinst[ii - 1].nz) {
+            SegInfo sg;
+            std::memset(&sg, 0, sizeof sg);
+            sg.task0 = h->task0[ii];
+            sg.first = ii;
+            sg.nx = I.nx;
+            sg.ny = I.ny;
+            sg.nz = I.nz;
+            sg.xsegs = (I.nx + 63) / 64;
+            sg.tpi = sg.xsegs * I.ny * I.nz;
+            h->segs.push_back(sg);
+        }
+    }
+
+    auto cleanup = [&](int code) {
+        delete h;
+        return code;
+    };
+    hipError_t e = hipMemcpyAsync(h->ws + L.off_inst, h->hinst.data(), sizeof(InstDev) * n_inst,
+                                  hipMemcpyHostToDevice, h->stream);
+    for (size_t b = 0; b < host_blobs.size() && e == hipSuccess; ++b)
+        e = hipMemcpyAsync(h->ws + blob_off[b], host_blobs[b].data(), host_blobs[b].size(),
+                           hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return cleanup(fail(LB_EDEVICE, "upload failed: %s", hipGetErrorString(e)));
+    st = zero_state(h);
+    if (st != LB_OK) return cleanup(st);
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess)
+        return cleanup(fail(LB_EDEVICE, "create: %s", hipGetErrorString(e)));
+    *out = h;
+    return LB_OK;
+}
+
+int lb_wave_step_n(lb_wave *h, int64_t n_steps)
+{
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (n_steps < 0) return fail(LB_EINVAL, "n_steps < 0");
+    if (h->nan_seen) return fail(LB_ENAN, "a previous force was not finite");
+    for (int64_t s = 0; s < n_steps; ++s) {
+        int st = enqueue_step(h);
+        if (st != LB_OK) return st;
+    }
+    return LB_OK;
+}
+
+int lb_surface_force(lb_wave *h, double *F_avg, int64_t *n_accum)
+{
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (!F_avg) return fail(LB_EINVAL, "F_avg is NULL");
+    std::vector<AccDev> acc(h->n);
+    HIP_TRY(hipMemcpyAsync(acc.data(), h->d_acc, sizeof(AccDev) * h->n, hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    int st = LB_OK;
+    for (int u = 0; u < h->n; ++u) {
+        const AccDev &A = acc[h->pos[u]];
+        if (n_accum) n_accum[u] = A.n;
+        for (int a = 0; a < 3; ++a) F_avg[3 * u + a] = A.n > 0 ? A.sum[a] / (double)A.n : 0.0;
+        if (A.nan) {
+            h->nan_seen = true;
+            st = fail(LB_ENAN, "instance %d: non-finite force", u);
+        } else if (A.n == 0 && st == LB_OK) {
+            st = fail(LB_EEMPTY, "instance %d: no step accumulated", u);
+        }
+    }
+    return st;
+}
+
+int lb_wave_destroy(lb_wave *h)
+{
+    delete h;
+    return LB_OK;
+}
+
+int lb_wave_steps_done(const lb_wave *h, int64_t *t)
+{
+    if (!h || !t) return fail(LB_EINVAL, "NULL argument");
+    *t = h->t;
+    return LB_OK;
+}
+
+int lb_wave_reset(lb_wave *h)
+{
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    return zero_state(h);
+}
+
+int lb_wave_state_view(const lb_wave *h, int32_t inst, lb_state_view *v)
+{
+    if (!h || !v) return fail(LB_EINVAL, "NULL argument");
+    if (inst < 0 || inst >= h->n) return fail(LB_EINVAL, "instance out of range");
+    const int ii = h->pos[inst];
+    const InstPlan &P = h->lay.p[inst];
+    const int b = (int)(steps_of(h, ii) & 1);
+    v->offset_bytes = P.off_buf[b];
+    v->plane_bytes = elem_bytes(h->storage) * (size_t)P.plane;
+    v->pitch = P.pitch;
+    v->elem_bytes = (int32_t)elem_bytes(h->storage);
+    v->scale = h->scale[inst];
+    return LB_OK;
+}
+
+int lb_wave_get_state(lb_wave *h, int32_t inst, double *host_fnew)
+{
+    if (!h || !host_fnew) return fail(LB_EINVAL, "NULL argument");
+    if (inst < 0 || inst >= h->n) return fail(LB_EINVAL, "instance out of range");
+    lb_state_view v;
+    int st = lb_wave_state_view(h, inst, &v);
+    if (st) return st;
+    const lb_wave_desc &d = h->desc[inst];
+    const int Q = 2 * d.dim + 1;
+    std::vector<uint8_t> raw(v.plane_bytes * Q);
+    HIP_TRY(hipMemcpyAsync(raw.data(), h->ws + v.offset_bytes, raw.size(), hipMemcpyDeviceToHost,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    const double inv = 1.0 / v.scale;
+    size_t c = 0;
+    for (int z = 0; z < d.nz; ++z)
+        for (int y = 0; y < d.ny; ++y)
+            for (int x = 0; x < d.nx; ++x, ++c) {
+                const size_t e = ((size_t)z * d.ny + y) * v.pitch + x;
+                for (int i = 0; i < Q; ++i)
+                    host_fnew[c * Q + i] =
+                        load_host(raw.data() + i * v.plane_bytes + e * v.elem_bytes, h->storage) * inv;
+            }
+    return LB_OK;
+}
+
+int lb_wave_set_state(lb_wave *h, int32_t inst, const double *host_fnew)
+{
+    if (!h || !host_fnew) return fail(LB_EINVAL, "NULL argument");
+    if (inst < 0 || inst >= h->n) return fail(LB_EINVAL, "instance out of range");
+    lb_state_view v;
+    int st = lb_wave_state_view(h, inst, &v);
+    if (st) return st;
+    const lb_wave_desc &d = h->desc[inst];
+    const int Q = 2 * d.dim + 1;
+    std::vector<uint8_t> raw(v.plane_bytes * Q, 0);
+    size_t c = 0;
+    for (int z = 0; z < d.nz; ++z)
+        for (int y = 0; y < d.ny; ++y)
+            for (int x = 0; x < d.nx; ++x, ++c) {
+                const size_t e = ((size_t)z * d.ny + y) * v.pitch + x;
+                for (int i = 0; i < Q; ++i)
+                    store_host(raw.data() + i * v.plane_bytes + e * v.elem_bytes, h->storage,
+                               host_fnew[c * Q + i] * v.scale);
+            }
+    HIP_TRY(hipMemcpyAsync(h->ws + v.offset_bytes, raw.data(), raw.size(), hipMemcpyHostToDevice,
+                           h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_wave_force_trace(lb_wave *h, int32_t inst, double *host_F, int64_t n)
+{
+    if (!h || !host_F) return fail(LB_EINVAL, "NULL argument");
+    if (inst < 0 || inst >= h->n) return fail(LB_EINVAL, "instance out of range");
+    if (n < 0 || n > h->desc[inst].trace_steps)
+        return fail(LB_EINVAL, "n exceeds the trace capacity");
+    if (n == 0) return LB_OK;
+    HIP_TRY(hipMemcpyAsync(host_F, h->ws + h->lay.p[inst].off_trace, sizeof(double) * 3 * n,
+                           hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_wave_set_tile(lb_wave *h, int32_t cells_per_lane)
+{
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (cells_per_lane != 1 && cells_per_lane != 2 && cells_per_lane != 4)
+        return fail(LB_EINVAL, "cells_per_lane must be 1, 2 or 4");
+    // the segment table depends on the tile width
+    h->vx = cells_per_lane;
+    const int w = 64 * cells_per_lane;
+    for (int ii = 0; ii < h->n; ++ii) {
+        const InstDev &I = h->hinst[ii];
+        h->task0[ii + 1] = h->task0[ii] + ((I.nx + w - 1) / w) * I.ny * I.nz;
+    }
+    for (auto &sg : h->segs) {
+        sg.task0 = h->task0[sg.first];
+        sg.xsegs = (sg.nx + w - 1) / w;
+        sg.tpi = sg.xsegs * sg.ny * sg.nz;
+    }
+    return LB_OK;
+}
+
+int lb_wave_get_tile(const lb_wave *h, int32_t *cells_per_lane)
+{
+    if (!h || !cells_per_lane) return fail(LB_EINVAL, "NULL argument");
+    *cells_per_lane = h->vx;
+    return LB_OK;
+}
+
+int lb_wave_autotune(lb_wave *h, int32_t n_trial, double *best_ms)
+{
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (n_trial < 1) return fail(LB_EINVAL, "n_trial must be >= 1");
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    double best = 1e300;
+    int best_vx = 1;
+    const int cand[3] = {1, 2, 4};
+    for (int c : cand) {
+        int st = lb_wave_set_tile(h, c);
+        if (st) return st;
+        st = lb_wave_step_n(h, 2);  // warm-up
+        if (st) return st;
+        HIP_TRY(hipEventRecord(e0, h->stream));
+        st = lb_wave_step_n(h, n_trial);
+        if (st) return st;
+        HIP_TRY(hipEventRecord(e1, h->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        const double per = ms / n_trial;
+        if (per < best) {
+            best = per;
+            best_vx = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    int st = lb_wave_set_tile(h, best_vx);
+    if (st) return st;
+    if (best_ms) *best_ms = best;
+    st = zero_state(h);
+    if (st) return st;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+size_t lb_cavity_workspace_bytes(int32_t nx)
+{
+    if (nx < 16 || nx > kCavMaxNx) return 0;
+    return align_up(sizeof(double) * 2 * (size_t)nx);
+}
+
+int lb_cavity_calibrate(int32_t nx, double c0, double omega, double rho_a, double wall_phi,
+                        int32_t n_periods, int32_t n_fit, void *dev_workspace,
+                        size_t workspace_bytes, void *hip_stream, double *out, double *host_P)
+{
+    g_err.clear();
+    if (!out) return fail(LB_EINVAL, "out is NULL");
+    if (nx < 16 || nx > kCavMaxNx) return fail(LB_EINVAL, "nx must lie in [16, %d]", kCavMaxNx);
+    if (!(c0 > 0) || c0 > 1.0) return fail(LB_EUNSTABLE, "c0 must lie in (0, 1]");
+    if (!(omega > 0) || omega >= M_PI) return fail(LB_EINVAL, "omega must lie in (0, pi)");
+    if (!(wall_phi >= 0 && wall_phi < 1)) return fail(LB_EINVAL, "wall_phi must lie in [0, 1)");
+    if (n_fit < 1 || n_periods < n_fit) return fail(LB_EINVAL, "need 1 <= n_fit <= n_periods");
+    const double cosk = 1.0 - (1.0 - std::cos(omega)) / (c0 * c0);
+    if (!(cosk > -1.0 && cosk < 1.0)) return fail(LB_EINVAL, "omega has no lattice wavenumber");
+    if (!dev_workspace || workspace_bytes < lb_cavity_workspace_bytes(nx))
+        return fail(LB_ENOMEM, "workspace too small");
+    const double period = 2.0 * M_PI / omega;
+    const int64_t n_total = (int64_t)std::llround(n_periods * period);
+    const int64_t m = (int64_t)std::llround(n_fit * period);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    double *d_lock = static_cast<double *>(dev_workspace);
+    hipLaunchKernelGGL(cavity_kernel, dim3(1), dim3(kCavThreads), 0, st, nx, c0 * c0, omega,
+                       rho_a, wall_phi, n_total, m, d_lock);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> lock(2 * (size_t)nx);
+    HIP_TRY(hipMemcpyAsync(lock.data(), d_lock, sizeof(double) * 2 * nx, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    // complex amplitude P = (2/m) sum rho e^{-i w t}
+    std::vector<double> re(nx), im(nx);
+    for (int x = 0; x < nx; ++x) {
+        re[x] = 2.0 / (double)m * lock[x];
+        im[x] = -2.0 / (double)m * lock[nx + x];
+        if (host_P) {
+            host_P[2 * x] = re[x];
+            host_P[2 * x + 1] = im[x];
+        }
+    }
+    // least squares |P|^2 = a + b cos 2kx + c sin 2kx over 2 <= x <= nx-3
+    const double k = std::acos(cosk);
+    double M[3][4] = {{0}};
+    for (int x = 2; x <= nx - 3; ++x) {
+        const double row[3] = {1.0, std::cos(2 * k * x), std::sin(2 * k * x)};
+        const double y = re[x] * re[x] + im[x] * im[x];
+        for (int i = 0; i < 3; ++i) {
+            for (int j = 0; j < 3; ++j) M[i][j] += row[i] * row[j];
+            M[i][3] += row[i] * y;
+        }
+    }
+    for (int c = 0; c < 3; ++c) {  // Gaussian elimination with partial pivoting
+        int p = c;
+        for (int r = c + 1; r < 3; ++r)
+            if (std::fabs(M[r][c]) > std::fabs(M[p][c])) p = r;
+        for (int j = 0; j < 4; ++j) std::swap(M[c][j], M[p][j]);
+        if (M[c][c] == 0.0) return fail(LB_EINVAL, "degenerate fit");
+        for (int r = 0; r < 3; ++r) {
+            if (r == c) continue;
+            const double f = M[r][c] / M[c][c];
+            for (int j = c; j < 4; ++j) M[r][j] -= f * M[c][j];
+        }
+    }
+    const double a = M[0][3] / M[0][0], b = M[1][3] / M[1][1], c = M[2][3] / M[2][2];
+    const double A = std::sqrt(a + std::hypot(b, c));
+    const double x0 = std::atan2(c, b) / (2.0 * k);
+    const double spacing = M_PI / k;
+    const double centre = 0.5 * (nx - 1);
+    const double xm = x0 + std::floor((centre - x0) / spacing) * spacing;
+    out[0] = A;
+    out[1] = xm;
+    out[2] = k;
+    out[3] = a;
+    out[4] = b;
+    out[5] = c;
+    return LB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,287 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Fields are compared element by element as max|f_gpu - f_orc| / max|f_orc|
+after n steps (bound 1e-12 for FP64 storage, 2e-5 for FP32), the per-step
+force F(t) as max|dF| / max|F| (1e-11 FP64, 1e-4 FP32), the time average as a
+relative error.  Sizes are ragged (nx not a multiple of 64) and span several
+wave tiles; the state starts from seeded random populations so that every
+population and every rule is exercised from the first step.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+TOL_FIELD = {"f64": 1e-12, "f32": 2e-5}
+TOL_TRACE = {"f64": 1e-11, "f32": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_02346_amd as P
+    P.lib()
+    return P
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
+
+
+def gpu_run(P, p, n, storage, init=None, vx=1, trace=True):
+    h = P.LBWave([p], storage=storage, trace_steps=n if trace else 0)
+    h.set_tile(vx)
+    if init is not None:
+        h.set_state(0, init)
+    h.step(n)
+    out = {"fnew": h.get_state(0)}
+    if trace and p.get("surf_xyz") is not None:
+        out["F_trace"] = h.trace(0, n)
+        out["F_avg"], out["n_acc"] = h.force(allow_empty=True)
+    h.close()
+    return out
+
+
+def driven_object(dim, shape, c0=0.45, cp=0.55, R=3.0, n_surf=48, lam=None, avg_start=3):
+    nx = shape[-1]
+    ny = shape[-2]
+    nz = shape[0] if dim == 3 else 1
+    lam = lam or float(nx)
+    center = (nx * 0.55, ny / 2.0 + 0.3, nz / 2.0 - 0.2 if dim == 3 else 0.0)
+    Rs = R + 2.0
+    if dim == 2:
+        xyz, nrm, area = workloads.circle_surface(center, Rs, n_surf)
+    else:
+        xyz, nrm, area = workloads.fibonacci_surface(center, Rs, n_surf)
+    return {"dim": dim, "nx": nx, "ny": ny, "nz": nz, "xbc": "driven", "c0": c0, "rho0": 1.0,
+            "center": center, "radius": R, "cp": cp, "d": 4.0, "rho_a": 1.0,
+            "omega": 2 * np.pi * c0 / lam, "wall_phi": 0.99, "surf_xyz": xyz,
+            "surf_normal": nrm, "surf_area": area, "avg_start": avg_start}
+
+
+CASES = [
+    # dim, shape (z, y, x), x boundary, sound speed, storage, tile
+    (2, (37, 133), "driven", "object", "f64", 1),
+    (2, (20, 70), "periodic", "field", "f64", 2),
+    (2, (9, 200), "driven", "field", "f32", 4),
+    (3, (11, 19, 70), "driven", "object", "f64", 1),
+    (3, (7, 9, 129), "periodic", "field", "f64", 4),
+    (3, (6, 10, 150), "driven", "object", "f32", 2),
+    (3, (5, 6, 64), "periodic", "field", "f32", 1),
+]
+
+
+@pytest.mark.parametrize("dim,shape,xbc,speed,storage,vx", CASES)
+def test_field_parity(P, orc, dim, shape, xbc, speed, storage, vx):
+    say(f"field parity dim={dim} shape={shape} xbc={xbc} speed={speed} {storage} vx={vx}")
+    Q = 2 * dim + 1
+    ncell = int(np.prod(shape))
+    if speed == "object":
+        p = driven_object(dim, shape, R=2.5)
+        p["xbc"] = xbc
+    else:
+        cmax = 0.68 if dim == 2 else 0.56
+        p = {"dim": dim, "nx": shape[-1], "ny": shape[-2], "nz": shape[0] if dim == 3 else 1,
+             "xbc": xbc, "c0": 0.45, "c_field": workloads.random_c_field(31, shape, 0.45,
+                                                                          cmax - 0.45),
+             "rho_a": 0.7, "omega": 0.05, "wall_phi": 0.95}
+    init = workloads.random_state(17 + dim, ncell, Q)
+    for n in (1, 9, 24):
+        ref = orc.run(p, n, fnew_init=init, want_fields=True, want_trace=p.get("surf_xyz") is not None)
+        got = gpu_run(P, p, n, storage, init=init, vx=vx)
+        e = rel(got["fnew"], ref["fnew"])
+        say(f"  n={n} field rel err {e:.3e}")
+        assert e <= TOL_FIELD[storage]
+        if "F_trace" in got:
+            et = rel(got["F_trace"], ref["F_trace"])
+            say(f"  n={n} trace rel err {et:.3e}")
+            assert et <= TOL_TRACE[storage]
+            if n > p["avg_start"]:
+                assert got["n_acc"][0] == ref["n_acc"]
+
+
+@pytest.mark.parametrize("dim,storage", [(2, "f64"), (2, "f32"), (3, "f64"), (3, "f32")])
+def test_force_trace_parity_from_rest(P, orc, dim, storage):
+    # the paper's run: zero state, driven source, object, surface measurement
+    shape = (60, 96) if dim == 2 else (24, 24, 72)
+    p = driven_object(dim, shape, R=4.0, n_surf=64 if dim == 2 else 400, avg_start=150)
+    n = 400
+    say(f"force trace parity dim={dim} {storage} shape={shape} n={n}")
+    ref = orc.run(p, n, want_trace=True, want_fields=True)
+    got = gpu_run(P, p, n, storage)
+    et = rel(got["F_trace"], ref["F_trace"])
+    ef = rel(got["fnew"], ref["fnew"])
+    ea = abs(got["F_avg"][0, 0] - ref["F_avg"][0]) / abs(ref["F_avg"][0])
+    say(f"  trace {et:.3e} field {ef:.3e} avg {ea:.3e}")
+    assert got["n_acc"][0] == ref["n_acc"] == n - 150
+    assert et <= TOL_TRACE[storage] and ef <= TOL_FIELD[storage]
+    assert ea <= (1e-10 if storage == "f64" else 1e-3)
+
+
+def test_cylinder_workload_fp64(P, orc):
+    # The 2D workload in full: 128 x 64 D2Q5, 20 periods, average over the last 5.
+    cal = orc.cavity_calibration(128, 0.5, 2 * np.pi * 0.5 / 128)
+    p = workloads.cylinder_2d(cal["x_mid"], cal["k"])
+    n = p["n_steps"]
+    say(f"cylinder workload fp64 n={n}")
+    ref = orc.run(p, n, want_trace=True, want_fields=True)
+    got = gpu_run(P, p, n, "f64")
+    e = abs(got["F_avg"][0, 0] - ref["F_avg"][0]) / abs(ref["F_avg"][0])
+    say(f"  F gpu {got['F_avg'][0]} oracle {ref['F_avg']} rel {e:.3e}")
+    assert got["n_acc"][0] == ref["n_acc"] == 1280
+    assert e <= 1e-10
+    assert rel(got["F_trace"], ref["F_trace"]) <= 1e-10
+    assert rel(got["fnew"], ref["fnew"]) <= 1e-10
+
+
+def test_small_sphere_fp32(P, orc):
+    # 3D sphere, reduced box (64 x 32 x 32, lambda = 64, R = 3), 12 periods.
+    cal = orc.cavity_calibration(64, 0.5, 2 * np.pi * 0.5 / 64)
+    p = workloads.sphere_3d(cal["x_mid"], cal["k"], math.pi / 4, n_periods=12, avg_periods=5,
+                            shape=(64, 32, 32), lam=64.0, R=3.0, n_surf=512)
+    n = p["n_steps"]
+    say(f"small sphere fp32 n={n}")
+    ref = orc.run(p, n)
+    got = gpu_run(P, p, n, "f32", trace=True)
+    e = np.abs(got["F_avg"][0] - ref["F_avg"]).max() / abs(ref["F_avg"][0])
+    say(f"  F gpu {got['F_avg'][0]} oracle {ref['F_avg']} rel {e:.3e}")
+    assert e <= 1e-3
+
+
+def test_batched_uneven_instances(P, orc):
+    # Different shapes and run lengths in one handle; each instance must equal
+    # its own oracle run (instances that stop early stay frozen).
+    probs = []
+    for i, (shape, ms) in enumerate([((10, 12, 70), 40), ((8, 8, 64), 25), ((10, 12, 70), 33),
+                                     ((6, 14, 100), 40), ((8, 8, 64), 12)]):
+        p = driven_object(3, shape, R=2.0, n_surf=100, avg_start=5)
+        p["max_steps"] = ms
+        p["cp"] = 0.5 + 0.01 * i
+        probs.append(p)
+    say("batched uneven: 5 instances, 3 shapes, max_steps 12..40, 45 steps")
+    h = P.LBWave(probs, storage="f32", trace_steps=45)
+    inits = []
+    for i, p in enumerate(probs):
+        inits.append(workloads.random_state(40 + i, p["nx"] * p["ny"] * p["nz"], 7))
+        h.set_state(i, inits[i])
+    h.step(45)
+    F, nacc = h.force()
+    for i, p in enumerate(probs):
+        ref = orc.run(p, p["max_steps"], fnew_init=inits[i], want_fields=True, want_trace=True)
+        ef = rel(h.get_state(i), ref["fnew"])
+        et = rel(h.trace(i, p["max_steps"]), ref["F_trace"])
+        ea = np.abs(F[i] - ref["F_avg"]).max() / np.abs(ref["F_avg"]).max()
+        say(f"  inst {i} field {ef:.2e} trace {et:.2e} avg {ea:.2e} nacc {nacc[i]}")
+        assert nacc[i] == ref["n_acc"]
+        assert ef <= TOL_FIELD["f32"] and et <= TOL_TRACE["f32"] and ea <= 1e-3
+    h.close()
+
+
+def test_tiles_and_reset_are_bitwise_identical(P):
+    p = driven_object(3, (9, 13, 150), R=3.0, n_surf=200, avg_start=2)
+    say("tile variants and reset")
+    states, forces = [], []
+    h = P.LBWave([p], storage="f32")
+    for vx in (1, 2, 4):
+        h.reset()
+        h.set_tile(vx)
+        h.step(30)
+        states.append(h.get_state(0))
+        forces.append(h.force()[0])
+    h.close()
+    for s, f in zip(states[1:], forces[1:]):
+        assert np.array_equal(s, states[0])
+        assert np.array_equal(f, forces[0])
+
+
+def test_autotune_keeps_results(P):
+    p = driven_object(3, (16, 32, 96), R=4.0, n_surf=300, avg_start=2)
+    say("autotune")
+    h = P.LBWave([p], storage="f32")
+    ms = h.autotune(4)
+    assert ms > 0 and h.tile() in (1, 2, 4) and h.t == 0
+    h.step(20)
+    a = h.get_state(0)
+    h.set_tile(1)
+    h.reset()
+    h.step(20)
+    assert np.array_equal(a, h.get_state(0))
+    h.close()
+
+
+def test_state_view_matches_get_state(P):
+    import torch
+    p = driven_object(3, (5, 7, 80), R=2.0, n_surf=8)
+    for key in ("surf_xyz", "surf_normal", "surf_area"):
+        p.pop(key)
+    h = P.LBWave([p], storage="f32")
+    h.step(7)
+    v = h.state_view(0)
+    Q, pitch = 7, v.pitch
+    raw = h.ws[v.offset_bytes: v.offset_bytes + Q * v.plane_bytes].view(torch.float32)
+    planes = raw.reshape(Q, -1).cpu().numpy()
+    st = h.get_state(0)
+    nx, ny, nz = 80, 7, 5
+    for i in range(Q):
+        pl = planes[i][: nz * ny * pitch].reshape(nz, ny, pitch)[:, :, :nx].reshape(-1)
+        assert np.array_equal(pl.astype(np.float64) / v.scale, st[:, i])
+    with pytest.raises(P.LBError) as ei:
+        h.force()
+    assert ei.value.code == -7  # nothing measured without a surface
+    h.close()
+
+
+@pytest.mark.parametrize("nx,c0,lam", [(128, 0.5, 128.0), (64, 1 / 3, 64.0), (96, 1 / 3, 96.0)])
+def test_cavity_calibration_parity(P, orc, nx, c0, lam):
+    om = 2 * np.pi * c0 / lam
+    say(f"cavity nx={nx} c0={c0:.4f}")
+    ref = orc.cavity_calibration(nx, c0, om)
+    got = P.cavity_calibrate(nx, c0, om)
+    say(f"  A {got['A']} vs {ref['A']}, x_mid {got['x_mid']} vs {ref['x_mid']}")
+    assert got["k"] == pytest.approx(ref["k"], rel=1e-13)
+    assert got["A"] == pytest.approx(ref["A"], rel=1e-10)
+    assert got["x_mid"] == pytest.approx(ref["x_mid"], abs=1e-8)
+    assert rel(got["P"], ref["P"]) <= 1e-10
+
+
+def test_full_size_sphere_fields(P, orc):
+    # The 3D workload's lattice (256 x 128 x 128, FP32) in the launch
+    # configuration the benchmark times: a few steps from a seeded random
+    # state compared over every cell, plus the force at each step.
+    cal_x, k = 126.63, 2 * np.pi / 256
+    p = workloads.sphere_3d(cal_x, k, math.pi / 4)
+    p["avg_start"] = 0
+    ncell = 256 * 128 * 128
+    init = workloads.random_state(77, ncell, 7, scale=0.05)
+    n = 3
+    say("full-size sphere fields fp32, 3 steps")
+    ref = orc.run(p, n, fnew_init=init, want_fields=True, want_trace=True)
+    got = gpu_run(P, p, n, "f32", init=init)
+    ef = rel(got["fnew"], ref["fnew"])
+    et = rel(got["F_trace"], ref["F_trace"])
+    say(f"  field {ef:.3e} trace {et:.3e}")
+    assert ef <= TOL_FIELD["f32"] and et <= TOL_TRACE["f32"]
+
+
+def test_step_zero_and_errors(P):
+    p = driven_object(2, (10, 40), R=2.0, n_surf=16, avg_start=0)
+    h = P.LBWave([p], storage="f64")
+    h.step(0)
+    assert h.t == 0
+    F, nacc = h.force(allow_empty=True)
+    assert nacc[0] == 0 and np.all(F == 0)
+    with pytest.raises(P.LBError):
+        h.step(-1)
+    with pytest.raises(P.LBError):
+        h.set_tile(3)
+    h.close()
