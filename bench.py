@@ -44,6 +44,11 @@ def parse():
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=800)
+    ap.add_argument("--variant", default=None,
+                    help="step-kernel variant 'cells_per_lane,x_mode,nontemporal' (skips autotune)")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="time only the step kernel (no surface) and the copy reference; for "
+                         "counter runs")
     return ap.parse_args()
 
 
@@ -62,7 +67,7 @@ def problems(x_mid, k, with_surface=True):
 
 def kernel_source_sha():
     h = hashlib.sha256()
-    for f in ("lb_kernels.hpp", "lb_wave.hip"):
+    for f in ("lb_kernels.hpp",):
         with open(os.path.join(ROOT, "paper_2404_02346_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -121,11 +126,47 @@ def main():
     probs = problems(x_mid, k)
     cells = N_POS * SHAPE[0] * SHAPE[1] * SHAPE[2]
     Q, s = 7, {"f32": 4, "f16": 2, "bf16": 2}[args.storage]
+    fixed = tuple(int(v) for v in args.variant.split(",")) if args.variant else None
+
+    if args.kernel_only:
+        # step kernel alone, then the copy of the same byte count, K launches each
+        g = P.LBWave(problems(x_mid, k, with_surface=False), storage=args.storage, stream=stream)
+        if fixed:
+            g.set_variant(*fixed)
+        g.step(args.warmup)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.step(args.steps)
+        e1.record(stream)
+        e1.synchronize()
+        kms = e0.elapsed_time(e1) / args.steps
+        variant = g.variant()
+        g.close()
+        del g
+        half = 2 * Q * s * cells // 2
+        a_buf = torch.empty(half, dtype=torch.uint8, device="cuda")
+        b_buf = torch.empty(half, dtype=torch.uint8, device="cuda")
+        e0.record(stream)
+        for _ in range(args.steps):
+            P.stream_copy(a_buf, b_buf, half, stream)
+        e1.record(stream)
+        e1.synchronize()
+        cms = e0.elapsed_time(e1) / args.steps
+        print(json.dumps({"mode": "kernel-only", "variant": variant, "storage": args.storage,
+                          "launches": args.steps, "step_kernel_ms": kms,
+                          "step_kernel_gbs": 2 * half / kms / 1e6, "copy_bytes": 2 * half,
+                          "copy_ms": cms, "copy_gbs": 2 * half / cms / 1e6}), flush=True)
+        return
 
     # --- whole hot path: step kernel + surface measurement, 16 instances ---
     h = P.LBWave(probs, storage=args.storage, stream=stream)
-    tune_ms = h.autotune(6)
-    tile = h.tile()
+    if fixed:
+        h.set_variant(*fixed)
+        tune_ms = None
+    else:
+        tune_ms = h.autotune(6)
+    variant = h.variant()
+    tile = variant[0]
     h.step(args.warmup)
     h.reset()  # the timed steps start the run from rest
     torch.cuda.synchronize()
@@ -142,7 +183,7 @@ def main():
 
     # --- dominant kernel alone (same instances and tile, no surface) timed with events ---
     g = P.LBWave(problems(x_mid, k, with_surface=False), storage=args.storage, stream=stream)
-    g.set_tile(tile)
+    g.set_variant(*variant)
     g.step(10)
     n_k = min(max(args.steps // 10, 50), 1000)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -157,9 +198,24 @@ def main():
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.storage)
 
+    # --- copy reference: the same bytes through one read and one write stream ---
+    half = bytes_per_launch // 2
+    a_buf = torch.empty(half, dtype=torch.uint8, device="cuda")
+    b_buf = torch.empty(half, dtype=torch.uint8, device="cuda")
+    for _ in range(3):
+        P.stream_copy(a_buf, b_buf, half, stream)
+    e0.record(stream)
+    n_c = 20
+    for _ in range(n_c):
+        P.stream_copy(a_buf, b_buf, half, stream)
+    e1.record(stream)
+    e1.synchronize()
+    copy_gbs = 2 * half / (e0.elapsed_time(e1) / n_c * 1e-3) / 1e9
+    del a_buf, b_buf
+
     # --- plain single-instance rate for the forces/s comparison ---
     one = P.LBWave([probs[7]], storage=args.storage, stream=stream)
-    one.set_tile(tile)
+    one.set_variant(*variant)
     one.step(10)
     torch.cuda.synchronize()
     n1 = 400
@@ -188,21 +244,25 @@ def main():
                         "2048 Fibonacci surface points, 16 positions kh in [0, pi/2] batched "
                         "in one handle, 30 periods (15360 steps), average over the last 10",
             "instances": N_POS, "cells_per_step": cells, "storage": args.storage,
-            "cells_per_lane": tile, "x_antinode": round(x_mid, 4), "Pa": cal["Pa"],
+            "kernel_variant": {"cells_per_lane": variant[0], "x_mode": variant[1],
+                               "nontemporal": variant[2]},
+            "x_antinode": round(x_mid, 4), "Pa": cal["Pa"],
         },
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": f"step_kernel<3,{args.storage},{tile}>",
+            "kernel": "step_kernel<3,{},{},{},{}>".format(args.storage, *variant),
             "kernel_ms": round(kernel_ms, 5),
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            "copy_reference_gbs": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4),
         },
         "forces_per_s": {
             "batched_16": round(N_POS / (n_run * ms_per_step * 1e-3), 3),
             "plain_single": round(1.0 / (n_run * single_ms * 1e-3), 3),
         },
-        "autotune_ms_per_step": round(tune_ms, 4),
+        "autotune_ms_per_step": None if tune_ms is None else round(tune_ms, 4),
     }
     if full_run:
         out["forces_x"] = [float(v) for v in F[:, 0]]

@@ -1,0 +1,79 @@
+/*
+ * lb_mlp.h -- C ABI of the MLP surrogate of the time-averaged acoustic
+ * radiation force (BF16 MFMA forward, backward and Adam on gfx950).
+ *
+ * The network maps three normalised inputs (k R, the position phase k h and
+ * the contrast c_p/c0, each mapped to [-1, 1] by the caller) to the force
+ * normalised by the small-sphere scale F0 = pi R^3 Pa^2 k / (3 rho0 c0^2) of
+ * eq. ARF_Gorkov_3D (with it F/F0 tends to f1 sin 2kh as kR -> 0).  It is
+ * trained on forces computed by the wave lattice Boltzmann library
+ * (lb_wave.h), which stays the reference and the fallback outside the
+ * training box.
+ *
+ * Architecture (fixed): 3 -> 256 -> 256 -> 256 -> 256 -> 1, exact-erf GELU
+ * after each hidden layer, linear output.  Parameters are FP32 masters, laid
+ * out layer by layer as W_l (out x in, row-major) followed by b_l; the
+ * matrix products run on MFMA with BF16 operands (weights, activations and
+ * back-propagated errors rounded to BF16) and FP32 accumulation; biases,
+ * pre-activations, the loss and Adam are FP32, the loss sum FP64.
+ *
+ * Conventions as in lb_wave.h: C linkage, lb_status return codes,
+ * lb_last_error(), pointers are host pointers unless named dev_*, the caller
+ * owns one 256-byte aligned device workspace and a HIP stream, the library
+ * never allocates device memory, a handle is not thread-safe.
+ */
+#ifndef LB_MLP_H
+#define LB_MLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_mlp lb_mlp;
+
+/* Number of FP32 parameters (198657). */
+int32_t lb_mlp_num_params(void);
+
+/* Workspace bytes for batches of up to max_batch samples (0 if max_batch < 1). */
+size_t lb_mlp_workspace_bytes(int32_t max_batch);
+
+/* Create a handle on the caller's workspace and stream.  Parameters and the
+ * Adam state start at zero; load parameters with lb_mlp_set_params. */
+int lb_mlp_create(int32_t max_batch, void *dev_workspace, size_t workspace_bytes,
+                  void *hip_stream, lb_mlp **out);
+int lb_mlp_destroy(lb_mlp *h);  /* NULL-safe */
+
+/* Copy FP32 parameters in (also zeroes the Adam moments and step count) or
+ * out; both synchronise the stream. */
+int lb_mlp_set_params(lb_mlp *h, const float *host_params);
+int lb_mlp_get_params(lb_mlp *h, float *host_params);
+
+/* y = net(x) for B <= max_batch samples: dev_x B x 3 FP32, dev_y B FP32.
+ * Asynchronous on the handle's stream. */
+int lb_mlp_forward(lb_mlp *h, const float *dev_x, int32_t B, float *dev_y);
+
+/* Gradient of the mean squared error L = (1/B) sum (y - t)^2 with respect to
+ * every parameter, without updating (host_grads: lb_mlp_num_params() floats;
+ * host_loss may be NULL).  Synchronises the stream. */
+int lb_mlp_grad(lb_mlp *h, const float *dev_x, const float *dev_t, int32_t B, float *host_grads,
+                double *host_loss);
+
+/* One Adam step on the mean squared error of the batch (asynchronous);
+ * lb_mlp_last_loss() returns that batch's loss (synchronises). */
+int lb_mlp_train_step(lb_mlp *h, const float *dev_x, const float *dev_t, int32_t B, float lr,
+                      float beta1, float beta2, float eps);
+int lb_mlp_last_loss(lb_mlp *h, double *loss);
+
+/* One 16x16x32 BF16 MFMA tile D = A B (A 16 x 32, B 32 x 16, row-major BF16
+ * bits; D 16 x 16 row-major FP32), computed by the same fragment mapping as
+ * the network's products: a check of the matrix-core lane layout. */
+int lb_mlp_mfma_probe(const uint16_t *dev_A, const uint16_t *dev_B, float *dev_D,
+                      void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LB_MLP_H */

@@ -166,13 +166,30 @@ typedef struct lb_state_view {
 } lb_state_view;
 int lb_wave_state_view(const lb_wave *h, int32_t inst, lb_state_view *v);
 
-/* Tile shape of the step kernel: cells per lane along x (1, 2 or 4).
- * lb_wave_autotune times every shape for n_trial steps on the handle's own
- * instances, keeps the fastest, then resets the state (lb_wave_reset).
- * best_ms (may be NULL) receives the winning time per step in ms. */
+/* Variant of the step kernel:
+ *   cells_per_lane 1, 2 or 4: contiguous cells a lane moves with one vector
+ *     load/store per population (a wavefront covers 64 * cells_per_lane cells);
+ *   x_mode 0: the +x/-x neighbours are shifted across lanes; 1: they are read
+ *     with a vector load offset by one element (4- and 8-byte storage only);
+ *   nontemporal 0: plain loads and stores, 1: non-temporal stores,
+ *     2: non-temporal loads and stores.
+ * Every variant computes bit-identical results.  lb_wave_autotune times every
+ * valid variant for n_trial steps on the handle's own instances, keeps the
+ * fastest, then resets the state (lb_wave_reset); best_ms (may be NULL)
+ * receives the winning time per step in ms.  set_tile/get_tile change or read
+ * cells_per_lane only. */
+int lb_wave_set_variant(lb_wave *h, int32_t cells_per_lane, int32_t x_mode, int32_t nontemporal);
+int lb_wave_get_variant(const lb_wave *h, int32_t *cells_per_lane, int32_t *x_mode,
+                        int32_t *nontemporal);
 int lb_wave_set_tile(lb_wave *h, int32_t cells_per_lane);
 int lb_wave_get_tile(const lb_wave *h, int32_t *cells_per_lane);
 int lb_wave_autotune(lb_wave *h, int32_t n_trial, double *best_ms);
+
+/* Plain device-to-device copy of `bytes` (multiple of 16, 16-byte aligned
+ * pointers) on `hip_stream`, asynchronous.  A bandwidth reference for the
+ * step kernel's roofline: it moves 2 * bytes through HBM with one read and
+ * one write stream. */
+int lb_stream_copy(const void *dev_src, void *dev_dst, size_t bytes, void *hip_stream);
 
 /* ---- empty-cavity calibration of the driven standing wave ---- */
 

@@ -6,4 +6,4 @@ Castro-Avila et al., "A lattice Boltzmann approach for acoustic manipulation"
 (arXiv 2404.02346).
 """
 from .lbwave import (LBError, LBWave, STORAGE, cavity_calibrate, check,  # noqa: F401
-                     lib, make_descs, workspace_bytes)
+                     lib, make_descs, stream_copy, workspace_bytes)

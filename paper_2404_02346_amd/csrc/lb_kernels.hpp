@@ -6,9 +6,9 @@
 //
 // Population storage is structure-of-arrays: plane i (velocity i) holds the
 // cells row by row, x fastest, rows `pitch` elements apart (pitch is a
-// multiple of 64 elements so every row starts on a 256-byte boundary for
-// 4-byte storage).  Two state buffers alternate: the step that starts at
-// t reads buffer t & 1 (f^new of step t-1) and writes buffer (t + 1) & 1.
+// multiple of 64 elements, so every row starts on a 256-byte boundary for
+// 4-byte storage).  Two state buffers alternate: the step that starts at t
+// reads buffer t & 1 (f^new of step t-1) and writes buffer (t + 1) & 1.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,46 +20,75 @@ constexpr int kMaxSeg = 8;          // same-shape instance runs handled by one l
 constexpr int kStepThreads = 256;   // 4 wavefronts of 64 lanes
 
 // ---------------------------------------------------------------------------
-// Storage types and conversions
+// Storage types: raw element R, compute type C
 // ---------------------------------------------------------------------------
-struct bf16 {
-    uint16_t bits;
+struct bf16 {  // tag type for bfloat16 storage (raw bits in uint16_t)
 };
 
 template <typename S> struct StoreTraits;
 template <> struct StoreTraits<double> {
-    using C = double;  // compute type
-    __device__ static inline double load(const double *p) { return *p; }
-    __device__ static inline void store(double *p, double v) { *p = v; }
+    using R = double;
+    using C = double;
+    __device__ static inline C to_c(R v) { return v; }
+    __device__ static inline R to_r(C v) { return v; }
 };
 template <> struct StoreTraits<float> {
+    using R = float;
     using C = float;
-    __device__ static inline float load(const float *p) { return *p; }
-    __device__ static inline void store(float *p, float v) { *p = v; }
+    __device__ static inline C to_c(R v) { return v; }
+    __device__ static inline R to_r(C v) { return v; }
 };
 template <> struct StoreTraits<_Float16> {
+    using R = _Float16;
     using C = float;
-    __device__ static inline float load(const _Float16 *p) { return (float)*p; }
-    __device__ static inline void store(_Float16 *p, float v) { *p = (_Float16)v; }
+    __device__ static inline C to_c(R v) { return (float)v; }
+    __device__ static inline R to_r(C v) { return (_Float16)v; }
 };
 template <> struct StoreTraits<bf16> {
+    using R = uint16_t;
     using C = float;
-    __device__ static inline float load(const bf16 *p) {
-        return __uint_as_float(((uint32_t)p->bits) << 16);
-    }
-    __device__ static inline void store(bf16 *p, float v) {
+    __device__ static inline C to_c(R v) { return __uint_as_float(((uint32_t)v) << 16); }
+    __device__ static inline R to_r(C v) {
         // round to nearest, ties to even
         uint32_t u = __float_as_uint(v);
         u += 0x7FFFu + ((u >> 16) & 1u);
-        p->bits = (uint16_t)(u >> 16);
+        return (R)(u >> 16);
     }
 };
+
+template <typename R, int N> struct VecT {
+    using type = R __attribute__((ext_vector_type(N)));
+};
+template <typename R> struct VecT<R, 1> {
+    using type = R;
+};
+
+template <typename V, bool NT> __device__ inline V vload(const V *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <typename V, bool NT> __device__ inline void vstore(V *p, V v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+template <typename R, int N> __device__ inline R vget(const typename VecT<R, N>::type &v, int c)
+{
+    if constexpr (N == 1) return v;
+    else return v[c];
+}
+template <typename R, int N> __device__ inline void vset(typename VecT<R, N>::type &v, int c, R x)
+{
+    if constexpr (N == 1) v = x;
+    else v[c] = x;
+}
 
 // ---------------------------------------------------------------------------
 // Per-instance data (lives in the workspace)
 // ---------------------------------------------------------------------------
 struct SurfPt {
-    int32_t ix[3], iy[3], iz[3];  // stencil node coordinates (y, z already wrapped)
+    int32_t bx[3], by[3], bz[3];  // stencil nodes in moment-box coordinates
     int32_t pad;
     double w[9];                  // 1D kernel weights: wx[0..2], wy[0..2], wz[0..2]
     double nA[3];                 // outward normal times element size
@@ -85,9 +114,12 @@ struct InstDev {
     double omega, wall_phi;
     int64_t max_steps;       // frozen for t >= max_steps
     // measurement
-    int32_t n_surf, pad0;
+    int32_t mb_lo[3];        // moment box origin (cells whose rho, J the surface reads)
+    int32_t mb_n[3];         // moment box extent (0 -> no measurement)
+    void *mom[2];            // moment boxes (rho, Jx, Jy, Jz per cell, compute type) by step parity
+    int32_t n_surf, n_chunks;  // surface elements, 64-element chunks
     const SurfPt *surf;
-    double *contrib;         // n_surf x 4 per-element flux (x, y, z, unused)
+    double *part;            // 2 x n_chunks x 4 per-chunk flux sums by step parity
     double c0sq_force;       // c0^2 in the surface integral
     double force_scale;      // -1 / (rho0 * scale^2)
     int64_t avg_start;
@@ -105,19 +137,39 @@ struct SegInfo {
     int32_t pad;
 };
 
+// One launch = [reducer blocks][surface blocks][lattice blocks], a
+// three-stage pipeline over consecutive steps:
+//  * lattice blocks advance step t and store rho1, J1 of f(t) in the moment
+//    box of parity t & 1;
+//  * surface blocks interpolate F(t_meas = t - 1) from the moment box of
+//    parity t_meas & 1 and write one partial sum per 64 elements;
+//  * reducer blocks sum the partials of F(t_red = t - 2) in a fixed order,
+//    scale, trace and accumulate.
+// Every stage reads what an earlier launch wrote, so no stage waits on
+// another inside a launch.
 struct StepArgs {
     const InstDev *inst;
     int64_t t;
     int32_t nseg;
     int32_t ntask;
     SegInfo seg[kMaxSeg];
+    int32_t n_red, n_sb;
+    int64_t t_red, t_meas;
+    const int32_t *sb_inst;   // per surface block: internal instance
+    const int32_t *sb_chunk;  // per surface block: chunk of 64 elements
 };
 
 __device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ---------------------------------------------------------------------------
-// Fused pull-advection + collision + x sheets.  One wavefront task covers
-// 64*VX consecutive cells of one row; lane l handles x = x0 + l + 64 j.
+// Lattice part: fused pull-advection + collision + x sheets.  One wavefront
+// task covers 64*CPL consecutive cells of one row; lane l owns the CPL
+// contiguous cells xl = x0 + l*CPL ... and moves them with one vector load
+// and one vector store per population.  The +x / -x populations come from
+// the neighbouring cell: XM = 0 shifts them across lanes (one extra scalar
+// load per task end), XM = 1 loads them with a vector load offset by one
+// element.  NT = 0: plain loads and stores, 1: non-temporal stores,
+// 2: non-temporal loads and stores.
 //
 // Collision with tau = 1/2 (eq. LBM-Collision) and the equilibrium of
 // eq. feq_waves reduce, for these velocity sets (w_i / c_s^2 = 1/2,
@@ -126,17 +178,14 @@ __device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlan
 //   f^new_0    = 2 (1 - dim c^2) rho - f_0,
 // with c = c(x) the local sound speed.
 // ---------------------------------------------------------------------------
-template <int DIM, typename S, int VX>
-__global__ void __launch_bounds__(kStepThreads) step_kernel(StepArgs a)
+template <int DIM, typename S, int CPL, int XM, int NT>
+__device__ inline void lattice_task(const StepArgs &a, int task, int lane)
 {
     using T = StoreTraits<S>;
+    using R = typename T::R;
     using C = typename T::C;
+    using V = typename VecT<R, CPL>::type;
     constexpr int Q = 2 * DIM + 1;
-
-    const int wave = wave_uniform(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int task = blockIdx.x * (kStepThreads / 64) + wave;
-    if (task >= a.ntask) return;
 
     int s = 0;
 #pragma unroll
@@ -156,8 +205,8 @@ __global__ void __launch_bounds__(kStepThreads) step_kernel(StepArgs a)
     const int nx = sg.nx, ny = sg.ny, nz = sg.nz;
     const int pitch = I.pitch;
     const int64_t plane = I.plane;
-    const S *src = static_cast<const S *>(I.buf[a.t & 1]);
-    S *dst = static_cast<S *>(I.buf[(a.t + 1) & 1]);
+    const R *src = static_cast<const R *>(I.buf[a.t & 1]);
+    R *dst = static_cast<R *>(I.buf[(a.t + 1) & 1]);
     const bool driven = (I.xbc == 0);
     const int ym = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
@@ -168,35 +217,99 @@ __global__ void __launch_bounds__(kStepThreads) step_kernel(StepArgs a)
     const int64_t row_yp = ((int64_t)z * ny + yp) * pitch;
     const int64_t row_zm = ((int64_t)zm * ny + y) * pitch;
     const int64_t row_zp = ((int64_t)zp * ny + y) * pitch;
+
+    const int x0 = xs * 64 * CPL;
+    const int xl = x0 + lane * CPL;
+    const bool lane_in = xl < pitch;  // the vector lies inside the row (cells >= nx are padding)
+
+    C f[Q][CPL];
+    {
+        V v[Q];
+        if (lane_in) {
+            v[0] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + row + xl));
+            if (XM == 0) {
+                v[1] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + plane + row + xl));
+                v[2] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 2 * plane + row + xl));
+            } else {
+                // one element earlier / later: stays inside the buffer because the
+                // +x plane follows plane 0 and the -x plane precedes plane 3
+                v[1] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + plane + row + xl - 1));
+                v[2] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 2 * plane + row + xl + 1));
+            }
+            v[3] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 3 * plane + row_ym + xl));
+            v[4] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 4 * plane + row_yp + xl));
+            if (DIM == 3) {
+                v[5] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 5 * plane + row_zm + xl));
+                v[6] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 6 * plane + row_zp + xl));
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) v[i] = V{};
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) f[i][c] = T::to_c(vget<R, CPL>(v[i], c));
+    }
+    if (XM == 0) {
+        // +x arrives from x - 1, -x from x + 1: shift within the lane, then across lanes
+        const C from_left = __shfl_up(f[1][CPL - 1], 1);
+        const C from_right = __shfl_down(f[2][0], 1);
+#pragma unroll
+        for (int c = CPL - 1; c > 0; --c) f[1][c] = f[1][c - 1];
+#pragma unroll
+        for (int c = 0; c < CPL - 1; ++c) f[2][c] = f[2][c + 1];
+        f[1][0] = from_left;
+        f[2][CPL - 1] = from_right;
+        if (lane == 0 && x0 > 0) f[1][0] = T::to_c(src[plane + row + x0 - 1]);
+        if (lane == 63) {
+            const int xn = x0 + 64 * CPL;
+            f[2][CPL - 1] = (xn < nx) ? T::to_c(src[2 * plane + row + xn]) : C(0);
+        }
+    }
+    // the two ends of the row: nothing enters from outside (driven) or wrap (periodic)
+    if (xl == 0) f[1][0] = driven ? C(0) : T::to_c(src[plane + row + nx - 1]);
+    {
+        const int cl = nx - 1 - xl;
+        if (cl >= 0 && cl < CPL) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c)
+                if (c == cl) f[2][c] = driven ? C(0) : T::to_c(src[2 * plane + row]);
+        }
+    }
+
     const C c0sq = (C)I.c0sq;
     const bool in_box_yz = (I.bb_n[0] > 0) && (y >= I.bb_lo[1]) && (y < I.bb_lo[1] + I.bb_n[1]) &&
                            (DIM == 2 || ((z >= I.bb_lo[2]) && (z < I.bb_lo[2] + I.bb_n[2])));
     const C *c2box = static_cast<const C *>(I.c2box);
+    const bool in_mbox_yz = (I.mb_n[0] > 0) && (y >= I.mb_lo[1]) &&
+                            (y < I.mb_lo[1] + I.mb_n[1]) &&
+                            (DIM == 2 || ((z >= I.mb_lo[2]) && (z < I.mb_lo[2] + I.mb_n[2])));
 
+    V o[Q];
 #pragma unroll
-    for (int j = 0; j < VX; ++j) {
-        const int x = xs * 64 * VX + j * 64 + lane;
-        if (x >= nx) continue;
-        C f[Q];
-        f[0] = T::load(src + row + x);
-        if (x > 0)
-            f[1] = T::load(src + plane + row + x - 1);
-        else
-            f[1] = driven ? C(0) : T::load(src + plane + row + nx - 1);
-        if (x < nx - 1)
-            f[2] = T::load(src + 2 * plane + row + x + 1);
-        else
-            f[2] = driven ? C(0) : T::load(src + 2 * plane + row);
-        f[3] = T::load(src + 3 * plane + row_ym + x);
-        f[4] = T::load(src + 4 * plane + row_yp + x);
-        if (DIM == 3) {
-            f[5] = T::load(src + 5 * plane + row_zm + x);
-            f[6] = T::load(src + 6 * plane + row_zp + x);
+    for (int c = 0; c < CPL; ++c) {
+        const int x = xl + c;
+        C rho = f[0][c];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) rho += f[i][c];
+        if (in_mbox_yz) {
+            // rho1, J1 of the advected populations f(t) for the surface measurement
+            const int bx = x - I.mb_lo[0];
+            if (bx >= 0 && bx < I.mb_n[0] && x < nx) {
+                const int by = y - I.mb_lo[1];
+                const int bz = (DIM == 3) ? z - I.mb_lo[2] : 0;
+                using V4 = typename VecT<C, 4>::type;
+                V4 *m = static_cast<V4 *>(I.mom[a.t & 1]) +
+                        (((int64_t)bz * I.mb_n[1] + by) * I.mb_n[0] + bx);
+                V4 mv;
+                mv[0] = rho;
+                mv[1] = f[1][c] - f[2][c];
+                mv[2] = f[3][c] - f[4][c];
+                mv[3] = (DIM == 3) ? f[5][c] - f[6][c] : C(0);
+                *m = mv;
+            }
         }
-        C rho = f[0];
-#pragma unroll
-        for (int i = 1; i < Q; ++i) rho += f[i];
-
         C c2 = c0sq;
         if (in_box_yz) {
             const int bx = x - I.bb_lo[0];
@@ -206,16 +319,18 @@ __global__ void __launch_bounds__(kStepThreads) step_kernel(StepArgs a)
                 c2 = c2box[((int64_t)bz * I.bb_n[1] + by) * I.bb_n[0] + bx];
             }
         }
-
         C out[Q];
-        if (driven && (x == 0 || x == nx - 1)) {
+        if (x >= nx) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) out[i] = C(0);  // padding stays zero
+        } else if (driven && (x == 0 || x == nx - 1)) {
             // damped bounce-back of the pre-collision populations (eq. bounce-back)
             const C phi = (C)I.wall_phi;
-            out[0] = phi * f[0];
+            out[0] = phi * f[0][c];
 #pragma unroll
             for (int i = 1; i < Q; i += 2) {
-                out[i] = phi * f[i + 1];
-                out[i + 1] = phi * f[i];
+                out[i] = phi * f[i + 1][c];
+                out[i + 1] = phi * f[i][c];
             }
         } else if (driven && x == 1) {
             // imposed density with the cell's own momentum (eq. imposingfields)
@@ -224,148 +339,155 @@ __global__ void __launch_bounds__(kStepThreads) step_kernel(StepArgs a)
             out[0] = rs * ((C)1 - (C)DIM * c2);
 #pragma unroll
             for (int i = 1; i < Q; i += 2) {
-                const C Ja = f[i] - f[i + 1];
+                const C Ja = f[i][c] - f[i + 1][c];
                 out[i] = h * (c2 * rs + Ja);
                 out[i + 1] = h * (c2 * rs - Ja);
             }
         } else {
             const C c2rho = c2 * rho;
-            out[0] = (C)2 * ((C)1 - (C)DIM * c2) * rho - f[0];
+            out[0] = (C)2 * ((C)1 - (C)DIM * c2) * rho - f[0][c];
 #pragma unroll
             for (int i = 1; i < Q; i += 2) {
-                out[i] = c2rho - f[i + 1];
-                out[i + 1] = c2rho - f[i];
+                out[i] = c2rho - f[i + 1][c];
+                out[i + 1] = c2rho - f[i][c];
             }
         }
 #pragma unroll
-        for (int i = 0; i < Q; ++i) T::store(dst + i * plane + row + x, out[i]);
+        for (int i = 0; i < Q; ++i) vset<R, CPL>(o[i], c, T::to_r(out[i]));
+    }
+    if (lane_in) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+            vstore<V, (NT >= 1)>(reinterpret_cast<V *>(dst + i * plane + row + xl), o[i]);
     }
 }
 
 // ---------------------------------------------------------------------------
-// Surface interpolation (eq. InterpolatedFields with the 3-point kernel as a
-// tensor product) and per-element flux of eq. arf_integral_LBM.  Block:
-// 64 elements x NZ wavefronts, wavefront dz handles stencil plane dz.
-// Reads the state buffer f^new(t); at the stencil nodes (never on an x
-// sheet) its moments equal those of the advected populations f(t).
+// Surface part.  A block handles 64 elements of one instance; its four
+// wavefronts split the 3^DIM stencil nodes (node n goes to wavefront n % 4).
+// Interpolation of eq. InterpolatedFields with the 3-point kernel as a tensor
+// product from the moment box of f(t_meas), then the per-element flux of
+// eq. arf_integral_LBM,
+//   (-|J|^2/2 + c0^2 rho^2/2) n dS + J (J . n dS),
+// summed over the 64 elements in a fixed order into one partial per chunk.
 // ---------------------------------------------------------------------------
-template <int DIM, typename S>
-__global__ void __launch_bounds__(192) surface_interp_kernel(const InstDev *insts, int64_t t,
-                                                             int first_inst)
+template <int DIM, typename C>
+__device__ inline void surface_block(const StepArgs &a, int sb, double (*lds)[64][4])
 {
-    using T = StoreTraits<S>;
-    constexpr int Q = 2 * DIM + 1;
-    constexpr int NZ = (DIM == 3) ? 3 : 1;
-    __shared__ double part[NZ][64][4];
-
-    const InstDev &I = insts[first_inst + blockIdx.y];
-    if (I.max_steps > 0 && t >= I.max_steps) return;
+    constexpr int NN = (DIM == 3) ? 27 : 9;
+    constexpr int PER = (NN + 3) / 4;
     const int lane = threadIdx.x & 63;
-    const int dz = wave_uniform(threadIdx.x >> 6);
-    const int k = blockIdx.x * 64 + lane;
+    const int w = wave_uniform(threadIdx.x >> 6);
+    const InstDev &I = a.inst[a.sb_inst[sb]];
+    const int chunk = a.sb_chunk[sb];
+    const int k = chunk * 64 + lane;
     const bool live = k < I.n_surf;
-    const S *src = static_cast<const S *>(I.buf[(t + 1) & 1]);
-    const int64_t plane = I.plane;
-    const int pitch = I.pitch;
+    const C *mom = static_cast<const C *>(I.mom[a.t_meas & 1]);
+    const int mbx = I.mb_n[0], mby = I.mb_n[1];
 
     double rI = 0.0, Jx = 0.0, Jy = 0.0, Jz = 0.0;
     if (live) {
         const SurfPt &P = I.surf[k];
-        const int zc = P.iz[dz];
-        const double wz = P.w[6 + dz];
 #pragma unroll
-        for (int dy = 0; dy < 3; ++dy) {
-            const int64_t rowb = ((int64_t)zc * I.ny + P.iy[dy]) * pitch;
-            const double wyz = P.w[3 + dy] * wz;
-#pragma unroll
-            for (int dx = 0; dx < 3; ++dx) {
-                const S *p = src + rowb + P.ix[dx];
-                double f[Q];
-#pragma unroll
-                for (int i = 0; i < Q; ++i) f[i] = (double)T::load(p + i * plane);
-                double rho = f[0];
-#pragma unroll
-                for (int i = 1; i < Q; ++i) rho += f[i];
-                const double w = P.w[dx] * wyz;
-                rI += w * rho;
-                Jx += w * (f[1] - f[2]);
-                Jy += w * (f[3] - f[4]);
-                if (DIM == 3) Jz += w * (f[5] - f[6]);
+        for (int j = 0; j < PER; ++j) {
+            const int n = w + 4 * j;
+            if (n < NN) {
+                const int dx = n % 3, dy = (n / 3) % 3, dz = n / 9;
+                const C *m = mom + 4 * (((int64_t)P.bz[dz] * mby + P.by[dy]) * mbx + P.bx[dx]);
+                const double wt = P.w[dx] * P.w[3 + dy] * P.w[6 + dz];
+                rI += wt * (double)m[0];
+                Jx += wt * (double)m[1];
+                Jy += wt * (double)m[2];
+                Jz += wt * (double)m[3];
             }
         }
     }
-    part[dz][lane][0] = rI;
-    part[dz][lane][1] = Jx;
-    part[dz][lane][2] = Jy;
-    part[dz][lane][3] = Jz;
+    lds[w][lane][0] = rI;
+    lds[w][lane][1] = Jx;
+    lds[w][lane][2] = Jy;
+    lds[w][lane][3] = Jz;
     __syncthreads();
-    if (dz != 0 || !live) return;
-    rI = part[0][lane][0];
-    Jx = part[0][lane][1];
-    Jy = part[0][lane][2];
-    Jz = part[0][lane][3];
-#pragma unroll
-    for (int q = 1; q < NZ; ++q) {
-        rI += part[q][lane][0];
-        Jx += part[q][lane][1];
-        Jy += part[q][lane][2];
-        Jz += part[q][lane][3];
+    if (w != 0) return;
+    double fx = 0.0, fy = 0.0, fz = 0.0;
+    if (live) {
+        rI = lds[0][lane][0] + lds[1][lane][0] + lds[2][lane][0] + lds[3][lane][0];
+        Jx = lds[0][lane][1] + lds[1][lane][1] + lds[2][lane][1] + lds[3][lane][1];
+        Jy = lds[0][lane][2] + lds[1][lane][2] + lds[2][lane][2] + lds[3][lane][2];
+        Jz = lds[0][lane][3] + lds[1][lane][3] + lds[2][lane][3] + lds[3][lane][3];
+        const SurfPt &P = I.surf[k];
+        const double iso = -0.5 * (Jx * Jx + Jy * Jy + Jz * Jz) + 0.5 * I.c0sq_force * rI * rI;
+        const double Jn = Jx * P.nA[0] + Jy * P.nA[1] + Jz * P.nA[2];
+        fx = iso * P.nA[0] + Jx * Jn;
+        fy = iso * P.nA[1] + Jy * Jn;
+        fz = iso * P.nA[2] + Jz * Jn;
     }
-    const SurfPt &P = I.surf[k];
-    // (-|J|^2/2 + c0^2 rho^2/2) n dS + J (J . n dS)
-    const double iso = -0.5 * (Jx * Jx + Jy * Jy + Jz * Jz) + 0.5 * I.c0sq_force * rI * rI;
-    const double Jn = Jx * P.nA[0] + Jy * P.nA[1] + Jz * P.nA[2];
-    double *o = I.contrib + 4 * (int64_t)k;
-    o[0] = iso * P.nA[0] + Jx * Jn;
-    o[1] = iso * P.nA[1] + Jy * Jn;
-    o[2] = iso * P.nA[2] + Jz * Jn;
+    // fixed-order butterfly over the 64 lanes
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        fx += __shfl_xor(fx, off);
+        fy += __shfl_xor(fy, off);
+        fz += __shfl_xor(fz, off);
+    }
+    if (lane == 0) {
+        double *o = I.part + ((a.t_meas & 1) * I.n_chunks + chunk) * 4;
+        o[0] = fx;
+        o[1] = fy;
+        o[2] = fz;
+    }
 }
 
-// Sum of the per-element fluxes in a fixed order (deterministic), scaling,
-// trace and time accumulation.  One block of 256 threads per instance.
-__global__ void __launch_bounds__(256) surface_reduce_kernel(const InstDev *insts, int64_t t,
-                                                             int first_inst)
+// Reducer: F(t_red) of one instance from its chunk partials (written by the
+// previous launch), scaled, traced and accumulated.
+__device__ inline void reduce_block(const StepArgs &a, int ii)
 {
-    __shared__ double red[3][256];
-    const InstDev &I = insts[first_inst + blockIdx.x];
-    if (I.max_steps > 0 && t >= I.max_steps) return;
+    if (threadIdx.x != 0) return;
+    const InstDev &I = a.inst[ii];
     if (I.n_surf == 0) return;
+    const int64_t t = a.t_red;
+    if (I.max_steps > 0 && t >= I.max_steps) return;
+    const double *p = I.part + (t & 1) * I.n_chunks * 4;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int k = threadIdx.x; k < I.n_surf; k += 256) {
-        const double *o = I.contrib + 4 * (int64_t)k;
-        s0 += o[0];
-        s1 += o[1];
-        s2 += o[2];
+    for (int c = 0; c < I.n_chunks; ++c) {
+        s0 += p[4 * c];
+        s1 += p[4 * c + 1];
+        s2 += p[4 * c + 2];
     }
-    red[0][threadIdx.x] = s0;
-    red[1][threadIdx.x] = s1;
-    red[2][threadIdx.x] = s2;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            red[0][threadIdx.x] += red[0][threadIdx.x + w];
-            red[1][threadIdx.x] += red[1][threadIdx.x + w];
-            red[2][threadIdx.x] += red[2][threadIdx.x + w];
-        }
-        __syncthreads();
+    const double F[3] = {s0 * I.force_scale, s1 * I.force_scale, s2 * I.force_scale};
+    if (t < I.trace_cap) {
+        I.trace[3 * t + 0] = F[0];
+        I.trace[3 * t + 1] = F[1];
+        I.trace[3 * t + 2] = F[2];
     }
-    if (threadIdx.x == 0) {
-        double F[3] = {red[0][0] * I.force_scale, red[1][0] * I.force_scale,
-                       red[2][0] * I.force_scale};
-        if (t < I.trace_cap) {
-            I.trace[3 * t + 0] = F[0];
-            I.trace[3 * t + 1] = F[1];
-            I.trace[3 * t + 2] = F[2];
-        }
-        if (t >= I.avg_start) {
-            AccDev *acc = I.acc;
-            acc->sum[0] += F[0];
-            acc->sum[1] += F[1];
-            acc->sum[2] += F[2];
-            acc->n += 1;
-            if (!(isfinite(F[0]) && isfinite(F[1]) && isfinite(F[2]))) acc->nan = 1;
-        }
+    if (t >= I.avg_start) {
+        AccDev *acc = I.acc;
+        acc->sum[0] += F[0];
+        acc->sum[1] += F[1];
+        acc->sum[2] += F[2];
+        acc->n += 1;
+        if (!(isfinite(F[0]) && isfinite(F[1]) && isfinite(F[2]))) acc->nan = 1;
     }
+}
+
+template <int DIM, typename S, int CPL, int XM, int NT>
+__global__ void __launch_bounds__(kStepThreads) step_kernel(StepArgs a)
+{
+    __shared__ double lds[4][64][4];
+    const int b = blockIdx.x;
+    if (b < a.n_red) {
+        reduce_block(a, b);
+        return;
+    }
+    if (b < a.n_red + a.n_sb) {
+        const int sb = b - a.n_red;
+        const InstDev &I = a.inst[a.sb_inst[sb]];
+        if (I.max_steps > 0 && a.t_meas >= I.max_steps) return;
+        surface_block<DIM, typename StoreTraits<S>::C>(a, sb, lds);
+        return;
+    }
+    const int wave = wave_uniform(threadIdx.x >> 6);
+    const int task = (b - a.n_red - a.n_sb) * (kStepThreads / 64) + wave;
+    if (task >= a.ntask) return;
+    lattice_task<DIM, S, CPL, XM, NT>(a, task, threadIdx.x & 63);
 }
 
 // Fill with zeros (used instead of hipMemsetAsync so that every node of a
@@ -375,6 +497,26 @@ __global__ void zero_kernel(uint4 *p, int64_t n16)
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
         p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Plain copy (bandwidth reference for the roofline): each thread moves UNR
+// independent 16-byte words, consecutive threads consecutive words.
+template <int UNR, bool NT>
+__global__ void __launch_bounds__(256) copy_kernel(const uint4 *__restrict__ src,
+                                                    uint4 *__restrict__ dst, int64_t n16)
+{
+    const int64_t base = (int64_t)blockIdx.x * 256 * UNR + threadIdx.x;
+    uint4 v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        const int64_t i = base + (int64_t)u * 256;
+        if (i < n16) v[u] = vload<uint4, NT>(src + i);
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+        const int64_t i = base + (int64_t)u * 256;
+        if (i < n16) vstore<uint4, NT>(dst + i, v[u]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -404,14 +546,6 @@ cavity_kernel(int nx, double c0sq, double omega, double rho_a, double phi, int64
         np_[j] = 0.0;  // post-collision +x population of the cell
         nm_[j] = 0.0;  // post-collision -x population of the cell
     }
-    for (int j = 0; j < kCavPer; ++j) {
-        const int x = threadIdx.x + j * kCavThreads;
-        if (x < nx) {
-            gp[x] = 0.0;
-            gm[x] = 0.0;
-        }
-    }
-    __syncthreads();
     for (int64_t t = 0; t < n_total; ++t) {
         // publish last step's post-collision moving populations
 #pragma unroll

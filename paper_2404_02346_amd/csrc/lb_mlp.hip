@@ -1,0 +1,534 @@
+// MLP surrogate of the radiation force: BF16 MFMA forward and backward
+// kernels, Adam, and the C ABI of include/lb_mlp.h.
+//
+// Matrix products use v_mfma_f32_16x16x32_bf16: per 64-lane wavefront,
+// A (16 x 32) has lane l holding row l % 16, k = 8 (l / 16) .. + 7;
+// B (32 x 16) has lane l holding column l % 16, the same k range;
+// D (16 x 16) has lane l holding column l % 16, rows 4 (l / 16) .. + 3.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "../../include/lb_mlp.h"
+#include "../../include/lb_wave.h"
+
+int lbw_fail_msg(int code, const char *msg);  // lb_wave.hip
+
+namespace mlp {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLayers = 5;
+constexpr int kDims[kLayers + 1] = {3, 256, 256, 256, 256, 1};
+constexpr int kHidden = 256;
+
+constexpr int param_offset_w(int l)
+{
+    int off = 0;
+    for (int i = 0; i < l; ++i) off += kDims[i + 1] * kDims[i] + kDims[i + 1];
+    return off;
+}
+constexpr int param_offset_b(int l) { return param_offset_w(l) + kDims[l + 1] * kDims[l]; }
+constexpr int kParams = param_offset_w(kLayers);
+
+__device__ inline float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__host__ __device__ inline uint16_t f2bf(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+
+// exact GELU and its derivative
+__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ inline float gelu_d(float z)
+{
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
+           z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+enum Epi { EPI_BIAS_GELU = 0, EPI_BIAS = 1, EPI_STORE = 2, EPI_GELU_BWD = 3 };
+
+struct GemmArgs {
+    int M, N, K;
+    const uint16_t *A;  // A(m, k) = A[m * sam + k * sak]
+    int64_t sam, sak;
+    const uint16_t *B;  // B(k, n) = B[k * sbk + n * sbn]
+    int64_t sbk, sbn;
+    int epi;
+    const float *bias;   // N (EPI_BIAS_GELU, EPI_BIAS)
+    float *outf;         // FP32 output, row stride ldo
+    int64_t ldo;
+    uint16_t *outb;      // BF16 output (EPI_BIAS_GELU, EPI_GELU_BWD), row stride ldo
+    const float *zprev;  // pre-activation for GELU' (EPI_GELU_BWD), row stride ldo
+};
+
+constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;
+
+// C (M x N) = A (M x K) B (K x N), 64 x 64 per block, 4 wavefronts of 32 x 32
+// (2 x 2 MFMA tiles each), K in steps of 32 through LDS; then the epilogue.
+__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDK];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][LDK];
+    const int m_blk = blockIdx.y * TM, n_blk = blockIdx.x * TN;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = 0; k0 < g.K; k0 += TK) {
+#pragma unroll
+        for (int e = 0; e < (TM * TK) / 256; ++e) {
+            const int idx = tid + 256 * e;
+            const int r = idx >> 5, kk = idx & 31;
+            const int k = k0 + kk;
+            const int m = m_blk + r, n = n_blk + r;
+            As[r][kk] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0;
+            Bs[r][kk] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0;
+        }
+        __syncthreads();
+        const int kk = 8 * (lane >> 4);
+        bf16x8 af[2], bfr[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            const int row = wm * 32 + i * 16 + (lane & 15);
+            af[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s16x8 *>(&As[row][kk]));
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int col = wn * 32 + j * 16 + (lane & 15);
+            bfr[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s16x8 *>(&Bs[col][kk]));
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = m_blk + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
+                const int n = n_blk + wn * 32 + j * 16 + (lane & 15);
+                if (m >= g.M || n >= g.N) continue;
+                const float c = acc[i][j][v];
+                const int64_t o = (int64_t)m * g.ldo + n;
+                switch (g.epi) {
+                case EPI_BIAS_GELU: {
+                    const float z = c + g.bias[n];
+                    g.outf[o] = z;
+                    g.outb[o] = f2bf(gelu(z));
+                    break;
+                }
+                case EPI_BIAS: g.outf[o] = c + g.bias[n]; break;
+                case EPI_STORE: g.outf[o] = c; break;
+                default: {
+                    const float d = c * gelu_d(g.zprev[o]);
+                    g.outf[o] = d;
+                    g.outb[o] = f2bf(d);
+                }
+                }
+            }
+}
+
+__global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = f2bf(x[i]);
+}
+
+// delta = 2 (y - t) / B (FP32 and BF16), loss = sum (y - t)^2 / B in FP64 (one block)
+__global__ void __launch_bounds__(256) loss_kernel(const float *y, const float *t, int B,
+                                                   float *df, uint16_t *db, double *loss)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < B; b += 256) {
+        const float e = y[b] - t[b];
+        const float d = 2.0f * e / (float)B;
+        df[b] = d;
+        db[b] = f2bf(d);
+        s += (double)e * (double)e;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] / (double)B;
+}
+
+// db[n] = sum_b delta[b, n], one thread per column, batch order fixed
+__global__ void colsum_kernel(const float *delta, int B, int N, float *db)
+{
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    float s = 0.f;
+    for (int b = 0; b < B; ++b) s += delta[(int64_t)b * N + n];
+    db[n] = s;
+}
+
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, uint16_t *pb, int n,
+                            float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    pb[i] = f2bf(pi);
+}
+
+__global__ void mirror_kernel(const float *p, uint16_t *pb, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) pb[i] = f2bf(p[i]);
+}
+
+__global__ void zero_f32_kernel(float *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.f;
+}
+
+// one MFMA tile with the network's fragment mapping (lane-layout check)
+__global__ void __launch_bounds__(64) mfma_probe_kernel(const uint16_t *A, const uint16_t *B,
+                                                        float *D)
+{
+    const int lane = threadIdx.x;
+    const int kk = 8 * (lane >> 4);
+    s16x8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        a[e] = (short)A[(lane & 15) * 32 + kk + e];
+        b[e] = (short)B[(kk + e) * 16 + (lane & 15)];
+    }
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
+                                                  __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) D[(4 * (lane >> 4) + v) * 16 + (lane & 15)] = acc[v];
+}
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t p, g, m, v, pb;           // parameters, gradients, Adam moments, BF16 mirror
+    size_t xb;                       // BF16 input (B x 3)
+    size_t act[kLayers];             // BF16 activations a_1..a_4 (B x 256); act[0] unused
+    size_t z[kLayers];               // FP32 pre-activations z_0..z_3 (B x 256)
+    size_t y;                        // FP32 output (B)
+    size_t df[2], dbf[2];            // FP32 / BF16 errors, ping-pong (B x 256)
+    size_t loss;                     // FP64
+    size_t total;
+};
+
+Layout plan(int Bm)
+{
+    Layout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    L.p = take(4 * (size_t)kParams);
+    L.g = take(4 * (size_t)kParams);
+    L.m = take(4 * (size_t)kParams);
+    L.v = take(4 * (size_t)kParams);
+    L.pb = take(2 * (size_t)kParams);
+    L.xb = take(2 * 3 * (size_t)Bm);
+    for (int l = 0; l < kLayers; ++l) {
+        L.act[l] = take(2 * (size_t)kHidden * Bm);
+        L.z[l] = take(4 * (size_t)kHidden * Bm);
+    }
+    L.y = take(4 * (size_t)Bm);
+    for (int i = 0; i < 2; ++i) {
+        L.df[i] = take(4 * (size_t)kHidden * Bm);
+        L.dbf[i] = take(2 * (size_t)kHidden * Bm);
+    }
+    L.loss = take(8);
+    L.total = off;
+    return L;
+}
+
+}  // namespace mlp
+
+using namespace mlp;
+
+struct lb_mlp {
+    int Bm = 0;
+    char *ws = nullptr;
+    hipStream_t stream = nullptr;
+    Layout L;
+    int64_t step = 0;
+    template <typename T> T *at(size_t off) const { return reinterpret_cast<T *>(ws + off); }
+};
+
+namespace {
+
+#define MLP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return lbw_fail_msg(LB_EDEVICE, hipGetErrorString(e_));   \
+    } while (0)
+
+void gemm(const lb_mlp *h, const GemmArgs &g)
+{
+    const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
+    hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, h->stream, g);
+}
+
+GemmArgs base_args() { GemmArgs g; std::memset(&g, 0, sizeof g); return g; }
+
+// forward for B samples; keeps activations and pre-activations for backward
+void forward(const lb_mlp *h, const float *x, int B, float *y)
+{
+    const int64_t n3 = 3 * (int64_t)B;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, h->stream,
+                       x, h->at<uint16_t>(h->L.xb), n3);
+    const uint16_t *a = h->at<uint16_t>(h->L.xb);
+    for (int l = 0; l < kLayers; ++l) {
+        const int K = kDims[l], N = kDims[l + 1];
+        GemmArgs g = base_args();
+        g.M = B;
+        g.N = N;
+        g.K = K;
+        g.A = a;
+        g.sam = K;
+        g.sak = 1;
+        g.B = h->at<uint16_t>(h->L.pb) + param_offset_w(l);  // B(k, n) = W[n][k]
+        g.sbk = 1;
+        g.sbn = K;
+        g.bias = h->at<float>(h->L.p) + param_offset_b(l);
+        g.ldo = N;
+        if (l < kLayers - 1) {
+            g.epi = EPI_BIAS_GELU;
+            g.outf = h->at<float>(h->L.z[l]);
+            g.outb = h->at<uint16_t>(h->L.act[l + 1]);
+            a = g.outb;
+        } else {
+            g.epi = EPI_BIAS;
+            g.outf = y;
+        }
+        gemm(h, g);
+    }
+}
+
+// loss, gradients of every parameter into L.g
+void backward(const lb_mlp *h, const float *t, int B)
+{
+    float *y = h->at<float>(h->L.y);
+    int cur = 0;
+    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, h->stream, y, t, B,
+                       h->at<float>(h->L.df[cur]), h->at<uint16_t>(h->L.dbf[cur]),
+                       h->at<double>(h->L.loss));
+    for (int l = kLayers - 1; l >= 0; --l) {
+        const int K = kDims[l], N = kDims[l + 1];
+        const uint16_t *a_in = (l == 0) ? h->at<uint16_t>(h->L.xb) : h->at<uint16_t>(h->L.act[l]);
+        const uint16_t *dl = h->at<uint16_t>(h->L.dbf[cur]);
+        // dW_l (N x K) = delta_l^T (N x B) a_l (B x K)
+        GemmArgs g = base_args();
+        g.M = N;
+        g.N = K;
+        g.K = B;
+        g.A = dl;
+        g.sam = 1;
+        g.sak = N;
+        g.B = a_in;
+        g.sbk = K;
+        g.sbn = 1;
+        g.epi = EPI_STORE;
+        g.outf = h->at<float>(h->L.g) + param_offset_w(l);
+        g.ldo = K;
+        gemm(h, g);
+        hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, h->stream,
+                           h->at<float>(h->L.df[cur]), B, N, h->at<float>(h->L.g) + param_offset_b(l));
+        if (l == 0) break;
+        // delta_{l-1} (B x K) = (delta_l (B x N) W_l (N x K)) * gelu'(z_{l-1})
+        GemmArgs d = base_args();
+        d.M = B;
+        d.N = K;
+        d.K = N;
+        d.A = dl;
+        d.sam = N;
+        d.sak = 1;
+        d.B = h->at<uint16_t>(h->L.pb) + param_offset_w(l);  // B(k, n) = W[k][n]
+        d.sbk = K;
+        d.sbn = 1;
+        d.epi = EPI_GELU_BWD;
+        d.zprev = h->at<float>(h->L.z[l - 1]);
+        d.outf = h->at<float>(h->L.df[1 - cur]);
+        d.outb = h->at<uint16_t>(h->L.dbf[1 - cur]);
+        d.ldo = K;
+        gemm(h, d);
+        cur = 1 - cur;
+    }
+}
+
+int check_batch(const lb_mlp *h, int B)
+{
+    if (!h) return lbw_fail_msg(LB_EINVAL, "handle is NULL");
+    if (B < 1 || B > h->Bm) return lbw_fail_msg(LB_EINVAL, "batch outside 1 .. max_batch");
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t lb_mlp_num_params(void) { return kParams; }
+
+size_t lb_mlp_workspace_bytes(int32_t max_batch)
+{
+    if (max_batch < 1) return 0;
+    return plan(max_batch).total;
+}
+
+int lb_mlp_create(int32_t max_batch, void *dev_workspace, size_t workspace_bytes, void *hip_stream,
+                  lb_mlp **out)
+{
+    if (!out) return lbw_fail_msg(LB_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_batch < 1) return lbw_fail_msg(LB_EINVAL, "max_batch must be >= 1");
+    Layout L = plan(max_batch);
+    if (!dev_workspace || reinterpret_cast<uintptr_t>(dev_workspace) % kAlign)
+        return lbw_fail_msg(LB_ENOMEM, "workspace must be 256-byte aligned device memory");
+    if (workspace_bytes < L.total) return lbw_fail_msg(LB_ENOMEM, "workspace too small");
+    lb_mlp *h = new lb_mlp();
+    h->Bm = max_batch;
+    h->ws = static_cast<char *>(dev_workspace);
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    h->L = L;
+    const int64_t nz = (int64_t)(L.pb - L.p) / 4;  // parameters, gradients, moments
+    hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, h->stream,
+                       h->at<float>(L.p), nz);
+    hipLaunchKernelGGL(mirror_kernel, dim3((kParams + 255) / 256), dim3(256), 0, h->stream,
+                       h->at<float>(L.p), h->at<uint16_t>(L.pb), kParams);
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        delete h;
+        return lbw_fail_msg(LB_EDEVICE, hipGetErrorString(e));
+    }
+    *out = h;
+    return LB_OK;
+}
+
+int lb_mlp_destroy(lb_mlp *h)
+{
+    delete h;
+    return LB_OK;
+}
+
+int lb_mlp_set_params(lb_mlp *h, const float *host_params)
+{
+    if (!h || !host_params) return lbw_fail_msg(LB_EINVAL, "NULL argument");
+    MLP_TRY(hipMemcpyAsync(h->at<float>(h->L.p), host_params, 4 * (size_t)kParams,
+                           hipMemcpyHostToDevice, h->stream));
+    for (size_t off : {h->L.m, h->L.v})
+        hipLaunchKernelGGL(zero_f32_kernel, dim3((kParams + 255) / 256), dim3(256), 0, h->stream,
+                           h->at<float>(off), (int64_t)kParams);
+    hipLaunchKernelGGL(mirror_kernel, dim3((kParams + 255) / 256), dim3(256), 0, h->stream,
+                       h->at<float>(h->L.p), h->at<uint16_t>(h->L.pb), kParams);
+    MLP_TRY(hipGetLastError());
+    MLP_TRY(hipStreamSynchronize(h->stream));
+    h->step = 0;
+    return LB_OK;
+}
+
+int lb_mlp_get_params(lb_mlp *h, float *host_params)
+{
+    if (!h || !host_params) return lbw_fail_msg(LB_EINVAL, "NULL argument");
+    MLP_TRY(hipMemcpyAsync(host_params, h->at<float>(h->L.p), 4 * (size_t)kParams,
+                           hipMemcpyDeviceToHost, h->stream));
+    MLP_TRY(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_mlp_forward(lb_mlp *h, const float *dev_x, int32_t B, float *dev_y)
+{
+    int st = check_batch(h, B);
+    if (st) return st;
+    if (!dev_x || !dev_y) return lbw_fail_msg(LB_EINVAL, "NULL argument");
+    forward(h, dev_x, B, dev_y);
+    MLP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+int lb_mlp_grad(lb_mlp *h, const float *dev_x, const float *dev_t, int32_t B, float *host_grads,
+                double *host_loss)
+{
+    int st = check_batch(h, B);
+    if (st) return st;
+    if (!dev_x || !dev_t || !host_grads) return lbw_fail_msg(LB_EINVAL, "NULL argument");
+    forward(h, dev_x, B, h->at<float>(h->L.y));
+    backward(h, dev_t, B);
+    MLP_TRY(hipGetLastError());
+    MLP_TRY(hipMemcpyAsync(host_grads, h->at<float>(h->L.g), 4 * (size_t)kParams,
+                           hipMemcpyDeviceToHost, h->stream));
+    if (host_loss)
+        MLP_TRY(hipMemcpyAsync(host_loss, h->at<double>(h->L.loss), 8, hipMemcpyDeviceToHost,
+                               h->stream));
+    MLP_TRY(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_mlp_train_step(lb_mlp *h, const float *dev_x, const float *dev_t, int32_t B, float lr,
+                      float beta1, float beta2, float eps)
+{
+    int st = check_batch(h, B);
+    if (st) return st;
+    if (!dev_x || !dev_t) return lbw_fail_msg(LB_EINVAL, "NULL argument");
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return lbw_fail_msg(LB_EINVAL, "bad Adam hyper-parameters");
+    forward(h, dev_x, B, h->at<float>(h->L.y));
+    backward(h, dev_t, B);
+    h->step++;
+    const float c1 = 1.f - std::pow(beta1, (float)h->step);
+    const float c2 = 1.f - std::pow(beta2, (float)h->step);
+    hipLaunchKernelGGL(adam_kernel, dim3((kParams + 255) / 256), dim3(256), 0, h->stream,
+                       h->at<float>(h->L.p), h->at<float>(h->L.g), h->at<float>(h->L.m),
+                       h->at<float>(h->L.v), h->at<uint16_t>(h->L.pb), kParams, lr, beta1, beta2,
+                       eps, c1, c2);
+    MLP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+int lb_mlp_last_loss(lb_mlp *h, double *loss)
+{
+    if (!h || !loss) return lbw_fail_msg(LB_EINVAL, "NULL argument");
+    MLP_TRY(hipMemcpyAsync(loss, h->at<double>(h->L.loss), 8, hipMemcpyDeviceToHost, h->stream));
+    MLP_TRY(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_mlp_mfma_probe(const uint16_t *dev_A, const uint16_t *dev_B, float *dev_D, void *hip_stream)
+{
+    if (!dev_A || !dev_B || !dev_D) return lbw_fail_msg(LB_EINVAL, "NULL argument");
+    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(hip_stream),
+                       dev_A, dev_B, dev_D);
+    MLP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+}  // extern "C"

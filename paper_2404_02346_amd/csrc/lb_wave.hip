@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <climits>
 #include <limits>
 #include <numeric>
 #include <string>
@@ -144,7 +145,7 @@ void stencil(const lb_wave_desc &d, const double *P, SurfPt &s, long xn[3])
     for (int a = 0; a < 3; ++a) {
         if (a == 2 && d.dim == 2) {
             for (int o = 0; o < 3; ++o) {
-                s.iz[o] = 0;
+                s.bz[o] = 0;
                 s.w[6 + o] = (o == 0) ? 1.0 : 0.0;
             }
             continue;
@@ -155,18 +156,61 @@ void stencil(const lb_wave_desc &d, const double *P, SurfPt &s, long xn[3])
             const double w = roma3((double)node - P[a]);
             if (a == 0) {
                 xn[o] = node;
-                s.ix[o] = (int)node;
+                s.bx[o] = (int)node;
                 s.w[o] = w;
             } else if (a == 1) {
-                s.iy[o] = wrapi(node, nn[1]);
+                s.by[o] = wrapi(node, nn[1]);
                 s.w[3 + o] = w;
             } else {
-                s.iz[o] = wrapi(node, nn[2]);
+                s.bz[o] = wrapi(node, nn[2]);
                 s.w[6 + o] = w;
             }
         }
     }
     s.pad = 0;
+}
+
+// Box of the stencil nodes of all surface points.  Along y and z a box that
+// would cross the periodic boundary takes the whole extent.
+Box measure_box(const lb_wave_desc &d)
+{
+    Box b;
+    if (d.n_surf <= 0) return b;
+    const int nn[3] = {d.nx, d.ny, d.dim == 3 ? d.nz : 1};
+    long lo[3] = {LONG_MAX, LONG_MAX, LONG_MAX}, hi[3] = {LONG_MIN, LONG_MIN, LONG_MIN};
+    for (int k = 0; k < d.n_surf; ++k)
+        for (int a = 0; a < d.dim; ++a) {
+            const long c = std::lround(d.surf_xyz[3 * k + a]);
+            lo[a] = std::min(lo[a], c - 1);
+            hi[a] = std::max(hi[a], c + 1);
+        }
+    for (int a = 0; a < 3; ++a) {
+        if (a >= d.dim) {
+            b.lo[a] = 0;
+            b.n[a] = 1;
+        } else if (lo[a] >= 0 && hi[a] < nn[a]) {
+            b.lo[a] = (int)lo[a];
+            b.n[a] = (int)(hi[a] - lo[a] + 1);
+        } else {
+            b.lo[a] = 0;
+            b.n[a] = nn[a];
+        }
+    }
+    return b;
+}
+
+// Stencil nodes relative to the moment box (y, z wrapped first).
+void stencil_in_box(const lb_wave_desc &d, const double *P, const Box &mb, SurfPt &s)
+{
+    SurfPt g;
+    long xn[3];
+    stencil(d, P, g, xn);
+    s = g;
+    for (int o = 0; o < 3; ++o) {
+        s.bx[o] = g.bx[o] - mb.lo[0];
+        s.by[o] = g.by[o] - mb.lo[1];
+        s.bz[o] = g.bz[o] - mb.lo[2];
+    }
 }
 
 int check_one(const lb_wave_desc &d, const lb_wave_desc &d0, int idx)
@@ -257,14 +301,17 @@ int check_all(const lb_wave_desc *descs, int n)
 }
 
 struct InstPlan {
-    Box box;
+    Box box;   // sound speed differs from c0
+    Box mbox;  // cells whose moments the surface reads
     int pitch;
     int64_t plane;
-    size_t off_surf, off_contrib, off_trace, off_box, off_buf[2];
+    int n_chunks;
+    size_t off_surf, off_part, off_mom[2], off_trace, off_box, off_buf[2];
 };
 
 struct Layout {
-    size_t off_inst, off_acc, total;
+    size_t off_inst, off_acc, off_sbtab, total;
+    int n_sb_total;
     std::vector<InstPlan> p;
 };
 
@@ -276,6 +323,10 @@ Layout plan(const lb_wave_desc *descs, int n)
     off = align_up(off + sizeof(InstDev) * n);
     L.off_acc = off;
     off = align_up(off + sizeof(AccDev) * n);
+    L.n_sb_total = 0;
+    for (int i = 0; i < n; ++i) L.n_sb_total += (descs[i].n_surf + 63) / 64;
+    L.off_sbtab = off;
+    off = align_up(off + sizeof(int32_t) * 2 * (size_t)L.n_sb_total);
     L.p.resize(n);
     for (int i = 0; i < n; ++i) {
         const lb_wave_desc &d = descs[i];
@@ -284,10 +335,16 @@ Layout plan(const lb_wave_desc *descs, int n)
         P.box = sound_speed_box(d);
         P.pitch = (int)align_up((size_t)d.nx, 64);
         P.plane = (int64_t)P.pitch * d.ny * d.nz;
+        P.n_chunks = (d.n_surf + 63) / 64;
+        P.mbox = measure_box(d);
+        for (int b = 0; b < 2; ++b) {
+            P.off_mom[b] = off;
+            off = align_up(off + 4 * compute_bytes(d.storage) * P.mbox.cells());
+        }
         P.off_surf = off;
         off = align_up(off + sizeof(SurfPt) * d.n_surf);
-        P.off_contrib = off;
-        off = align_up(off + sizeof(double) * 4 * d.n_surf);
+        P.off_part = off;
+        off = align_up(off + sizeof(double) * 2 * 4 * (size_t)P.n_chunks);
         P.off_trace = off;
         off = align_up(off + sizeof(double) * 3 * (size_t)d.trace_steps);
         P.off_box = off;
@@ -345,7 +402,7 @@ inline void store_host(uint8_t *p, int storage, double v)
 }  // namespace
 
 struct lb_wave {
-    int n = 0, dim = 0, storage = 0, vx = 1;
+    int n = 0, dim = 0, storage = 0, vx = 1, xm = 0, nt = 0;
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
@@ -359,9 +416,13 @@ struct lb_wave {
     std::vector<double> scale;        // user order
     InstDev *d_inst = nullptr;
     AccDev *d_acc = nullptr;          // internal order
-    int max_surf = 0;
+    int32_t *d_sb_inst = nullptr;     // surface block table (internal order)
+    int32_t *d_sb_chunk = nullptr;
+    std::vector<int> sb_first;        // internal order, size n + 1
     bool any_surf = false;
-    int64_t t = 0;
+    int64_t t = 0;                    // lattice steps done
+    int64_t meas = 0;                 // steps whose chunk partials exist
+    int64_t red = 0;                  // steps reduced into the accumulators
     bool nan_seen = false;
 };
 
@@ -384,79 +445,108 @@ int active_prefix(const lb_wave *h, int64_t t)
     return n;
 }
 
-template <int DIM, typename S, int VX>
-void launch_step_t(const StepArgs &a, hipStream_t st)
+int prefix_alive(const lb_wave *h, int64_t t)
 {
-    const int blocks = (a.ntask + 3) / 4;
-    hipLaunchKernelGGL((step_kernel<DIM, S, VX>), dim3(blocks), dim3(kStepThreads), 0, st, a);
+    // instances are sorted by max_steps (longest first): those still alive at t form a prefix
+    if (t < 0) return 0;
+    return active_prefix(h, t);
+}
+
+template <int DIM, typename S, int CPL, int XM, int NT>
+void launch_t(const StepArgs &a, int blocks, hipStream_t st)
+{
+    hipLaunchKernelGGL((step_kernel<DIM, S, CPL, XM, NT>), dim3(blocks), dim3(kStepThreads), 0, st,
+                       a);
+}
+
+// Variants compiled per storage: 16-bit storage only shifts across lanes (its
+// elements are 2 bytes, too small for the offset vector load).
+template <int DIM, typename S, int CPL>
+void launch_c(const lb_wave *h, const StepArgs &a, int blocks)
+{
+    constexpr bool wide = sizeof(typename StoreTraits<S>::R) >= 4;
+    constexpr int XW = wide ? 1 : 0;
+    if (h->xm == 1 && wide) {
+        switch (h->nt) {
+        case 1: launch_t<DIM, S, CPL, XW, 1>(a, blocks, h->stream); break;
+        case 2: launch_t<DIM, S, CPL, XW, 2>(a, blocks, h->stream); break;
+        default: launch_t<DIM, S, CPL, XW, 0>(a, blocks, h->stream); break;
+        }
+    } else {
+        switch (h->nt) {
+        case 1: launch_t<DIM, S, CPL, 0, 1>(a, blocks, h->stream); break;
+        case 2: launch_t<DIM, S, CPL, 0, 2>(a, blocks, h->stream); break;
+        default: launch_t<DIM, S, CPL, 0, 0>(a, blocks, h->stream); break;
+        }
+    }
 }
 
 template <int DIM, typename S>
-void launch_step_s(const StepArgs &a, int vx, hipStream_t st)
+void launch_s(const lb_wave *h, const StepArgs &a, int blocks)
 {
-    switch (vx) {
-    case 2: launch_step_t<DIM, S, 2>(a, st); break;
-    case 4: launch_step_t<DIM, S, 4>(a, st); break;
-    default: launch_step_t<DIM, S, 1>(a, st); break;
+    switch (h->vx) {
+    case 2: launch_c<DIM, S, 2>(h, a, blocks); break;
+    case 4: launch_c<DIM, S, 4>(h, a, blocks); break;
+    default: launch_c<DIM, S, 1>(h, a, blocks); break;
     }
 }
 
-template <int DIM>
-void launch_step_d(const StepArgs &a, int storage, int vx, hipStream_t st)
+void launch(const lb_wave *h, const StepArgs &a, int blocks)
 {
-    switch (storage) {
-    case LB_F64: launch_step_s<DIM, double>(a, vx, st); break;
-    case LB_F32: launch_step_s<DIM, float>(a, vx, st); break;
-    case LB_F16: launch_step_s<DIM, _Float16>(a, vx, st); break;
-    default: launch_step_s<DIM, bf16>(a, vx, st); break;
-    }
-}
-
-template <int DIM>
-void launch_surface_d(const lb_wave *h, int64_t t, int n_active)
-{
-    const dim3 g((h->max_surf + 63) / 64, n_active);
-    const int thr = 64 * (DIM == 3 ? 3 : 1);
+    if (blocks <= 0) return;
+    const bool d2 = h->dim == 2;
     switch (h->storage) {
-    case LB_F64:
-        hipLaunchKernelGGL((surface_interp_kernel<DIM, double>), g, dim3(thr), 0, h->stream,
-                           h->d_inst, t, 0);
-        break;
-    case LB_F32:
-        hipLaunchKernelGGL((surface_interp_kernel<DIM, float>), g, dim3(thr), 0, h->stream,
-                           h->d_inst, t, 0);
-        break;
+    case LB_F64: d2 ? launch_s<2, double>(h, a, blocks) : launch_s<3, double>(h, a, blocks); break;
+    case LB_F32: d2 ? launch_s<2, float>(h, a, blocks) : launch_s<3, float>(h, a, blocks); break;
     case LB_F16:
-        hipLaunchKernelGGL((surface_interp_kernel<DIM, _Float16>), g, dim3(thr), 0, h->stream,
-                           h->d_inst, t, 0);
+        d2 ? launch_s<2, _Float16>(h, a, blocks) : launch_s<3, _Float16>(h, a, blocks);
         break;
-    default:
-        hipLaunchKernelGGL((surface_interp_kernel<DIM, bf16>), g, dim3(thr), 0, h->stream,
-                           h->d_inst, t, 0);
-        break;
+    default: d2 ? launch_s<2, bf16>(h, a, blocks) : launch_s<3, bf16>(h, a, blocks); break;
     }
-    hipLaunchKernelGGL(surface_reduce_kernel, dim3(n_active), dim3(256), 0, h->stream,
-                       h->d_inst, t, 0);
 }
 
-// One step for every active instance: fused step kernel(s), then the
-// surface measurement of the state it wrote.
+// Measurement part of a launch: partials of F(meas) if the newest state is
+// f^new(meas) and it has not been measured, reduction of F(red) if its
+// partials came from an earlier launch.  `newest` is the step whose f^new
+// the launch's lattice blocks read (t - 1), or the last completed step.
+void plan_measure(lb_wave *h, StepArgs &a, int64_t newest)
+{
+    a.n_red = 0;
+    a.n_sb = 0;
+    if (!h->any_surf) {
+        h->meas = h->red = newest + 1;
+        return;
+    }
+    if (h->red < h->meas) {
+        a.t_red = h->red;
+        a.n_red = prefix_alive(h, h->red);
+        h->red++;
+    }
+    if (newest >= 0 && h->meas == newest) {
+        a.t_meas = newest;
+        a.n_sb = h->sb_first[prefix_alive(h, newest)];
+        h->meas++;
+    }
+    a.sb_inst = h->d_sb_inst;
+    a.sb_chunk = h->d_sb_chunk;
+}
+
+// One lattice step for every live instance, with the measurement of the
+// previous step's state folded into the same launch.
 int enqueue_step(lb_wave *h)
 {
     const int64_t t = h->t;
     const int na = active_prefix(h, t);
-    if (na == 0) {
-        h->t++;
-        return LB_OK;
-    }
     const int ntask_active = h->task0[na];
+    StepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.inst = h->d_inst;
+    a.t = t;
+    plan_measure(h, a, t - 1);
     size_t s = 0;
-    while (s < h->segs.size() && h->segs[s].task0 < ntask_active) {
-        StepArgs a;
-        std::memset(&a, 0, sizeof a);
-        a.inst = h->d_inst;
-        a.t = t;
-        const int base = h->segs[s].task0;
+    bool first = true;
+    do {
+        const int base = s < h->segs.size() ? h->segs[s].task0 : 0;
         int k = 0;
         for (; k < kMaxSeg && s + k < h->segs.size() && h->segs[s + k].task0 < ntask_active; ++k) {
             a.seg[k] = h->segs[s + k];
@@ -465,21 +555,29 @@ int enqueue_step(lb_wave *h)
         const int end = (s + k < h->segs.size()) ? std::min(h->segs[s + k].task0, ntask_active)
                                                  : ntask_active;
         a.nseg = k;
-        a.ntask = end - base;
-        if (h->dim == 2)
-            launch_step_d<2>(a, h->storage, h->vx, h->stream);
-        else
-            launch_step_d<3>(a, h->storage, h->vx, h->stream);
+        a.ntask = k > 0 ? end - base : 0;
+        if (!first) a.n_red = a.n_sb = 0;
+        launch(h, a, a.n_red + a.n_sb + (a.ntask + 3) / 4);
+        first = false;
         s += k;
-    }
-    if (h->any_surf) {
-        if (h->dim == 2)
-            launch_surface_d<2>(h, t, na);
-        else
-            launch_surface_d<3>(h, t, na);
-    }
+    } while (s < h->segs.size() && h->segs[s].task0 < ntask_active);
     HIP_TRY(hipGetLastError());
     h->t++;
+    return LB_OK;
+}
+
+// Finish the measurement of every completed step (two launches at most).
+int flush_measure(lb_wave *h)
+{
+    while (h->red < h->t) {
+        StepArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.inst = h->d_inst;
+        a.t = h->t;
+        plan_measure(h, a, h->t - 1);
+        launch(h, a, a.n_red + a.n_sb);
+        HIP_TRY(hipGetLastError());
+    }
     return LB_OK;
 }
 
@@ -509,12 +607,15 @@ int zero_state(lb_wave *h)
     }
     int st = zero_region(h, h->lay.off_acc, sizeof(AccDev) * h->n);
     if (st) return st;
-    h->t = 0;
+    h->t = h->meas = h->red = 0;
     h->nan_seen = false;
     return LB_OK;
 }
 
 }  // namespace
+
+// error reporting shared with the MLP translation unit
+int lbw_fail_msg(int code, const char *msg) { return fail(code, "%s", msg); }
 
 // ===========================================================================
 // C ABI
@@ -565,6 +666,8 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
     }
     h->d_inst = reinterpret_cast<InstDev *>(h->ws + L.off_inst);
     h->d_acc = reinterpret_cast<AccDev *>(h->ws + L.off_acc);
+    h->d_sb_inst = reinterpret_cast<int32_t *>(h->ws + L.off_sbtab);
+    h->d_sb_chunk = h->d_sb_inst + L.n_sb_total;
     h->vx = 1;
 
     // internal order: longest runs first (so the active set is a prefix),
@@ -616,16 +719,22 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
         I.omega = d.omega;
         I.wall_phi = d.wall_phi;
         I.max_steps = d.max_steps;
+        for (int a = 0; a < 3; ++a) {
+            I.mb_lo[a] = P.mbox.lo[a];
+            I.mb_n[a] = P.mbox.n[a];
+        }
+        I.mom[0] = h->ws + P.off_mom[0];
+        I.mom[1] = h->ws + P.off_mom[1];
         I.n_surf = d.n_surf;
+        I.n_chunks = P.n_chunks;
         I.surf = reinterpret_cast<const SurfPt *>(h->ws + P.off_surf);
-        I.contrib = reinterpret_cast<double *>(h->ws + P.off_contrib);
+        I.part = reinterpret_cast<double *>(h->ws + P.off_part);
         I.c0sq_force = d.c0 * d.c0;
         I.force_scale = -1.0 / (d.rho0 * sc * sc);
         I.avg_start = d.avg_start;
         I.acc = h->d_acc + ii;
         I.trace = reinterpret_cast<double *>(h->ws + P.off_trace);
         I.trace_cap = d.trace_steps;
-        h->max_surf = std::max(h->max_surf, d.n_surf);
         if (d.n_surf > 0) h->any_surf = true;
 
         const int xsegs = (d.nx + 63) / 64;
@@ -636,8 +745,7 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
             std::vector<uint8_t> blob(sizeof(SurfPt) * d.n_surf);
             SurfPt *sp = reinterpret_cast<SurfPt *>(blob.data());
             for (int k = 0; k < d.n_surf; ++k) {
-                long xn[3];
-                stencil(d, d.surf_xyz + 3 * k, sp[k], xn);
+                stencil_in_box(d, d.surf_xyz + 3 * k, P.mbox, sp[k]);
                 for (int a = 0; a < 3; ++a) sp[k].nA[a] = d.surf_normal[3 * k + a] * d.surf_area[k];
             }
             host_blobs.push_back(std::move(blob));
@@ -668,6 +776,23 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
             host_blobs.push_back(std::move(blob));
             blob_off.push_back(P.off_box);
         }
+    }
+    // surface block table in internal order
+    std::vector<int32_t> sbtab(2 * (size_t)L.n_sb_total);
+    h->sb_first.assign(n_inst + 1, 0);
+    for (int ii = 0; ii < n_inst; ++ii) {
+        const int nc = L.p[h->order[ii]].n_chunks;
+        h->sb_first[ii + 1] = h->sb_first[ii] + nc;
+        for (int c = 0; c < nc; ++c) {
+            sbtab[h->sb_first[ii] + c] = ii;
+            sbtab[L.n_sb_total + h->sb_first[ii] + c] = c;
+        }
+    }
+    if (L.n_sb_total > 0) {
+        std::vector<uint8_t> blob(sizeof(int32_t) * sbtab.size());
+        std::memcpy(blob.data(), sbtab.data(), blob.size());
+        host_blobs.push_back(std::move(blob));
+        blob_off.push_back(L.off_sbtab);
     }
     // segments: maximal runs of equal shape in internal order
     for (int ii = 0; ii < n_inst; ++ii) {
@@ -715,7 +840,7 @@ int lb_wave_step_n(lb_wave *h, int64_t n_steps)
         int st = enqueue_step(h);
         if (st != LB_OK) return st;
     }
-    return LB_OK;
+    return flush_measure(h);
 }
 
 int lb_surface_force(lb_wave *h, double *F_avg, int64_t *n_accum)
@@ -839,13 +964,19 @@ int lb_wave_force_trace(lb_wave *h, int32_t inst, double *host_F, int64_t n)
     return LB_OK;
 }
 
-int lb_wave_set_tile(lb_wave *h, int32_t cells_per_lane)
+int lb_wave_set_variant(lb_wave *h, int32_t cells_per_lane, int32_t x_mode, int32_t nontemporal)
 {
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     if (cells_per_lane != 1 && cells_per_lane != 2 && cells_per_lane != 4)
         return fail(LB_EINVAL, "cells_per_lane must be 1, 2 or 4");
-    // the segment table depends on the tile width
+    if (x_mode != 0 && x_mode != 1) return fail(LB_EINVAL, "x_mode must be 0 or 1");
+    if (x_mode == 1 && elem_bytes(h->storage) < 4)
+        return fail(LB_EINVAL, "x_mode 1 needs 4- or 8-byte storage");
+    if (nontemporal < 0 || nontemporal > 2) return fail(LB_EINVAL, "nontemporal must be 0, 1 or 2");
+    // the task table depends on the row tile width
     h->vx = cells_per_lane;
+    h->xm = x_mode;
+    h->nt = nontemporal;
     const int w = 64 * cells_per_lane;
     for (int ii = 0; ii < h->n; ++ii) {
         const InstDev &I = h->hinst[ii];
@@ -857,6 +988,22 @@ int lb_wave_set_tile(lb_wave *h, int32_t cells_per_lane)
         sg.tpi = sg.xsegs * sg.ny * sg.nz;
     }
     return LB_OK;
+}
+
+int lb_wave_get_variant(const lb_wave *h, int32_t *cells_per_lane, int32_t *x_mode,
+                        int32_t *nontemporal)
+{
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (cells_per_lane) *cells_per_lane = h->vx;
+    if (x_mode) *x_mode = h->xm;
+    if (nontemporal) *nontemporal = h->nt;
+    return LB_OK;
+}
+
+int lb_wave_set_tile(lb_wave *h, int32_t cells_per_lane)
+{
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    return lb_wave_set_variant(h, cells_per_lane, h->xm, h->nt);
 }
 
 int lb_wave_get_tile(const lb_wave *h, int32_t *cells_per_lane)
@@ -874,34 +1021,56 @@ int lb_wave_autotune(lb_wave *h, int32_t n_trial, double *best_ms)
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     double best = 1e300;
-    int best_vx = 1;
-    const int cand[3] = {1, 2, 4};
-    for (int c : cand) {
-        int st = lb_wave_set_tile(h, c);
-        if (st) return st;
-        st = lb_wave_step_n(h, 2);  // warm-up
-        if (st) return st;
-        HIP_TRY(hipEventRecord(e0, h->stream));
-        st = lb_wave_step_n(h, n_trial);
-        if (st) return st;
-        HIP_TRY(hipEventRecord(e1, h->stream));
-        HIP_TRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-        const double per = ms / n_trial;
-        if (per < best) {
-            best = per;
-            best_vx = c;
-        }
-    }
+    int bv[3] = {1, 0, 0};
+    const int xm_max = elem_bytes(h->storage) >= 4 ? 1 : 0;
+    for (int cpl : {1, 2, 4})
+        for (int xm = 0; xm <= xm_max; ++xm)
+            for (int nt = 0; nt <= 2; ++nt) {
+                int st = lb_wave_set_variant(h, cpl, xm, nt);
+                if (st) return st;
+                st = lb_wave_step_n(h, 2);  // warm-up
+                if (st) return st;
+                HIP_TRY(hipEventRecord(e0, h->stream));
+                st = lb_wave_step_n(h, n_trial);
+                if (st) return st;
+                HIP_TRY(hipEventRecord(e1, h->stream));
+                HIP_TRY(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+                const double per = ms / n_trial;
+                if (per < best) {
+                    best = per;
+                    bv[0] = cpl;
+                    bv[1] = xm;
+                    bv[2] = nt;
+                }
+            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    int st = lb_wave_set_tile(h, best_vx);
+    int st = lb_wave_set_variant(h, bv[0], bv[1], bv[2]);
     if (st) return st;
     if (best_ms) *best_ms = best;
     st = zero_state(h);
     if (st) return st;
     HIP_TRY(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+int lb_stream_copy(const void *dev_src, void *dev_dst, size_t bytes, void *hip_stream)
+{
+    if (!dev_src || !dev_dst) return fail(LB_EINVAL, "NULL pointer");
+    if (bytes % 16 || reinterpret_cast<uintptr_t>(dev_src) % 16 ||
+        reinterpret_cast<uintptr_t>(dev_dst) % 16)
+        return fail(LB_EINVAL, "pointers and size must be multiples of 16 bytes");
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (n16 == 0) return LB_OK;
+    constexpr int UNR = 4;
+    const int64_t blocks = (n16 + 256 * UNR - 1) / (256 * UNR);
+    if (blocks > INT32_MAX) return fail(LB_EINVAL, "copy too large");
+    hipLaunchKernelGGL((copy_kernel<UNR, false>), dim3((unsigned)blocks), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), static_cast<const uint4 *>(dev_src),
+                       static_cast<uint4 *>(dev_dst), n16);
+    HIP_TRY(hipGetLastError());
     return LB_OK;
 }
 

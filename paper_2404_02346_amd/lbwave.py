@@ -74,9 +74,13 @@ def lib():
         L.lb_wave_set_state.argtypes = [vp, C.c_int32, _dp]
         L.lb_wave_force_trace.argtypes = [vp, C.c_int32, _dp, C.c_int64]
         L.lb_wave_state_view.argtypes = [vp, C.c_int32, C.POINTER(StateView)]
+        L.lb_wave_set_variant.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
+        L.lb_wave_get_variant.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_int32)]
         L.lb_wave_set_tile.argtypes = [vp, C.c_int32]
         L.lb_wave_get_tile.argtypes = [vp, C.POINTER(C.c_int32)]
         L.lb_wave_autotune.argtypes = [vp, C.c_int32, _dp]
+        L.lb_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
         L.lb_cavity_workspace_bytes.argtypes = [C.c_int32]
         L.lb_cavity_workspace_bytes.restype = C.c_size_t
         L.lb_cavity_calibrate.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double,
@@ -242,6 +246,15 @@ class LBWave:
     def set_tile(self, cells_per_lane: int):
         _check(lib().lb_wave_set_tile(self._h, int(cells_per_lane)))
 
+    def set_variant(self, cells_per_lane: int, x_mode: int = 0, nontemporal: int = 0):
+        _check(lib().lb_wave_set_variant(self._h, int(cells_per_lane), int(x_mode),
+                                         int(nontemporal)))
+
+    def variant(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().lb_wave_get_variant(self._h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
     def tile(self) -> int:
         v = C.c_int32()
         _check(lib().lb_wave_get_tile(self._h, C.byref(v)))
@@ -251,6 +264,12 @@ class LBWave:
         ms = C.c_double()
         _check(lib().lb_wave_autotune(self._h, int(n_trial), C.byref(ms)))
         return ms.value
+
+
+def stream_copy(src, dst, nbytes: int, stream=None):
+    """Plain device copy (lb_stream_copy): the bandwidth reference of the roofline."""
+    _check(lib().lb_stream_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                                int(nbytes), _stream_handle(stream)))
 
 
 def cavity_calibrate(nx: int, c0: float, omega: float, rho_a: float = 1.0,

@@ -40,7 +40,10 @@ def rel(a, b):
 
 def gpu_run(P, p, n, storage, init=None, vx=1, trace=True):
     h = P.LBWave([p], storage=storage, trace_steps=n if trace else 0)
-    h.set_tile(vx)
+    if isinstance(vx, tuple):
+        h.set_variant(*vx)
+    else:
+        h.set_tile(vx)
     if init is not None:
         h.set_state(0, init)
     h.step(n)
@@ -70,14 +73,16 @@ def driven_object(dim, shape, c0=0.45, cp=0.55, R=3.0, n_surf=48, lam=None, avg_
 
 
 CASES = [
-    # dim, shape (z, y, x), x boundary, sound speed, storage, tile
-    (2, (37, 133), "driven", "object", "f64", 1),
-    (2, (20, 70), "periodic", "field", "f64", 2),
-    (2, (9, 200), "driven", "field", "f32", 4),
-    (3, (11, 19, 70), "driven", "object", "f64", 1),
-    (3, (7, 9, 129), "periodic", "field", "f64", 4),
-    (3, (6, 10, 150), "driven", "object", "f32", 2),
-    (3, (5, 6, 64), "periodic", "field", "f32", 1),
+    # dim, shape (z, y, x), x boundary, sound speed, storage, variant (cells/lane, x mode, nt)
+    (2, (37, 133), "driven", "object", "f64", (1, 0, 0)),
+    (2, (20, 70), "periodic", "field", "f64", (2, 1, 1)),
+    (2, (9, 200), "driven", "field", "f32", (4, 1, 0)),
+    (3, (11, 19, 70), "driven", "object", "f64", (1, 1, 0)),
+    (3, (7, 9, 129), "periodic", "field", "f64", (4, 0, 1)),
+    (3, (6, 10, 150), "driven", "object", "f32", (2, 0, 1)),
+    (3, (5, 6, 64), "periodic", "field", "f32", (1, 1, 1)),
+    (3, (4, 5, 130), "periodic", "field", "f32", (4, 1, 2)),
+    (3, (4, 5, 300), "driven", "object", "f32", (4, 0, 0)),
 ]
 
 
@@ -187,21 +192,40 @@ def test_batched_uneven_instances(P, orc):
     h.close()
 
 
-def test_tiles_and_reset_are_bitwise_identical(P):
+def test_variants_and_reset_are_bitwise_identical(P):
     p = driven_object(3, (9, 13, 150), R=3.0, n_surf=200, avg_start=2)
-    say("tile variants and reset")
+    say("kernel variants and reset")
     states, forces = [], []
     h = P.LBWave([p], storage="f32")
-    for vx in (1, 2, 4):
+    variants = [(c, x, n) for c in (1, 2, 4) for x in (0, 1) for n in (0, 1, 2)]
+    for v in variants:
         h.reset()
-        h.set_tile(vx)
+        h.set_variant(*v)
         h.step(30)
         states.append(h.get_state(0))
         forces.append(h.force()[0])
     h.close()
-    for s, f in zip(states[1:], forces[1:]):
-        assert np.array_equal(s, states[0])
-        assert np.array_equal(f, forces[0])
+    for v, s, f in zip(variants[1:], states[1:], forces[1:]):
+        assert np.array_equal(s, states[0]), v
+        assert np.array_equal(f, forces[0]), v
+
+
+def test_sixteen_bit_variants_agree(P):
+    p = driven_object(3, (6, 8, 100), R=2.0, n_surf=64, avg_start=2)
+    for storage in ("f16", "bf16"):
+        h = P.LBWave([p], storage=storage)
+        with pytest.raises(P.LBError):
+            h.set_variant(1, 1, 0)  # offset vector loads need 4-byte elements
+        ref = None
+        for v in [(c, 0, n) for c in (1, 2, 4) for n in (0, 1, 2)]:
+            h.reset()
+            h.set_variant(*v)
+            h.step(20)
+            st = h.get_state(0)
+            if ref is None:
+                ref = st
+            assert np.array_equal(st, ref), (storage, v)
+        h.close()
 
 
 def test_autotune_keeps_results(P):
@@ -210,9 +234,10 @@ def test_autotune_keeps_results(P):
     h = P.LBWave([p], storage="f32")
     ms = h.autotune(4)
     assert ms > 0 and h.tile() in (1, 2, 4) and h.t == 0
+    say(f"  chosen variant {h.variant()} at {ms:.4f} ms/step")
     h.step(20)
     a = h.get_state(0)
-    h.set_tile(1)
+    h.set_variant(1, 0, 0)
     h.reset()
     h.step(20)
     assert np.array_equal(a, h.get_state(0))
