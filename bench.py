@@ -46,6 +46,13 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--variant", default=None,
                     help="step-kernel variant 'cells_per_lane,x_mode,nontemporal' (skips autotune)")
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "batch"],
+                    help="sphere: the 16-position 3D sphere (default); batch: the seeded uneven "
+                         "batch of boxes (forces/s batched vs plain)")
+    ap.add_argument("--batch-seed", type=int, default=2404)
+    ap.add_argument("--batch-n", type=int, default=256)
+    ap.add_argument("--graph", type=int, default=64,
+                    help="replay steady steps as captured HIP graphs of this many steps (0 = off)")
     ap.add_argument("--kernel-only", action="store_true",
                     help="time only the step kernel (no surface) and the copy reference; for "
                          "counter runs")
@@ -107,6 +114,59 @@ def cpu_baseline(x_mid, k, n_steps):
                       f"256x128x128 lattice with surface measurement ({dt:.1f} s)"}
 
 
+def batch_workload(args):
+    """The uneven batch: every instance to its own length in one handle, vs one at a time."""
+    import torch
+    import paper_2404_02346_amd as P
+    import workloads
+    from paper_2404_02346_amd import surrogate as S
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    cal = S.calibrate_edges(workloads.BATCH_EDGES)
+    probs, info = workloads.batch(args.batch_seed, args.batch_n,
+                                  {e: c["x_mid"] for e, c in cal.items()},
+                                  {e: c["k"] for e, c in cal.items()}, return_draws=True)
+    r = S.run_batch(probs, storage=args.storage, graph=args.graph)
+    # plain: each instance alone on the GPU, step time measured per box edge
+    plain_s, per_edge = 0.0, {}
+    for e in sorted({int(p["nx"]) for p in probs}):
+        group = [p for p in probs if int(p["nx"]) == e]
+        h = P.LBWave([group[0]], storage=args.storage, stream=stream)
+        h.autotune(4)
+        h.set_graph(args.graph)
+        h.step(10)
+        torch.cuda.synchronize()
+        n1 = 300
+        t0 = time.perf_counter()
+        h.step(n1)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / n1 * 1e3
+        h.close()
+        per_edge[e] = ms
+        plain_s += ms * 1e-3 * sum(int(p["n_steps"]) for p in group)
+    n = len(probs)
+    out = {
+        "metric": METRIC, "value": round(r["updates"] / r["seconds"] / 1e6, 1), "unit": "MLUPS",
+        "n_gpus": 1, "steps": max(int(p["n_steps"]) for p in probs), "warmup": 0,
+        "ms_per_step": round(r["seconds"] / max(int(p["n_steps"]) for p in probs) * 1e3, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.storage, "data": "synthetic",
+        "config": {"workload": f"uneven batch: {n} seeded cubic boxes (seed {args.batch_seed}), "
+                               "edge in {64,96,128,192} = lambda, R~U[4,16], c_p/c0~U[0.8,1.5], "
+                               "kh~U[0,pi/2], c0=1/3, 30 periods each (last 10 averaged), one "
+                               "handle, graph-replayed steps",
+                   "instances": n, "updates": r["updates"], "rejected_draws": info["rejected"],
+                   "kernel_variant": r["variant"], "graph_chunk": args.graph},
+        "forces_per_s": {"batched": round(n / r["seconds"], 3),
+                         "plain_one_at_a_time": round(n / plain_s, 3),
+                         "batched_over_plain": round(plain_s / r["seconds"], 3)},
+        "batched_seconds": round(r["seconds"], 2), "plain_seconds_estimated": round(plain_s, 2),
+        "plain_ms_per_step_by_edge": {str(k): round(v, 4) for k, v in per_edge.items()},
+        "forces_x": [float(v) for v in r["F"][:, 0]],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -114,6 +174,9 @@ def main():
               "(the batched instances would shard by instance; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        batch_workload(args)
+        return
     import torch
     import paper_2404_02346_amd as P
     import workloads  # noqa: F401
@@ -133,6 +196,7 @@ def main():
         g = P.LBWave(problems(x_mid, k, with_surface=False), storage=args.storage, stream=stream)
         if fixed:
             g.set_variant(*fixed)
+        g.set_graph(args.graph)
         g.step(args.warmup)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -167,6 +231,7 @@ def main():
         tune_ms = h.autotune(6)
     variant = h.variant()
     tile = variant[0]
+    h.set_graph(args.graph)
     h.step(args.warmup)
     h.reset()  # the timed steps start the run from rest
     torch.cuda.synchronize()
@@ -184,6 +249,7 @@ def main():
     # --- dominant kernel alone (same instances and tile, no surface) timed with events ---
     g = P.LBWave(problems(x_mid, k, with_surface=False), storage=args.storage, stream=stream)
     g.set_variant(*variant)
+    g.set_graph(args.graph)
     g.step(10)
     n_k = min(max(args.steps // 10, 50), 1000)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -216,6 +282,7 @@ def main():
     # --- plain single-instance rate for the forces/s comparison ---
     one = P.LBWave([probs[7]], storage=args.storage, stream=stream)
     one.set_variant(*variant)
+    one.set_graph(args.graph)
     one.step(10)
     torch.cuda.synchronize()
     n1 = 400
@@ -246,6 +313,7 @@ def main():
             "instances": N_POS, "cells_per_step": cells, "storage": args.storage,
             "kernel_variant": {"cells_per_lane": variant[0], "x_mode": variant[1],
                                "nontemporal": variant[2]},
+            "graph_chunk": args.graph,
             "x_antinode": round(x_mid, 4), "Pa": cal["Pa"],
         },
         "roofline": {

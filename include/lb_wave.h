@@ -185,6 +185,13 @@ int lb_wave_set_tile(lb_wave *h, int32_t cells_per_lane);
 int lb_wave_get_tile(const lb_wave *h, int32_t *cells_per_lane);
 int lb_wave_autotune(lb_wave *h, int32_t n_trial, double *best_ms);
 
+/* Replay steady steps as captured HIP graphs of `chunk` steps (0 = off,
+ * otherwise 2..4096).  A sequence is captured once per launch shape and
+ * replayed at any step (the kernels read the step counter from the
+ * workspace); steps where the measurement pipeline starts or an instance
+ * stops are launched one by one.  Results are bit-identical either way. */
+int lb_wave_set_graph(lb_wave *h, int32_t chunk);
+
 /* Plain device-to-device copy of `bytes` (multiple of 16, 16-byte aligned
  * pointers) on `hip_stream`, asynchronous.  A bandwidth reference for the
  * step kernel's roofline: it moves 2 * bytes through HBM with one read and

@@ -147,14 +147,19 @@ struct SegInfo {
 //    scale, trace and accumulate.
 // Every stage reads what an earlier launch wrote, so no stage waits on
 // another inside a launch.
+// The lattice step of a launch is t = *tp + dt: the counter lives in device
+// memory so that a captured sequence of launches can be replayed at any t.
 struct StepArgs {
     const InstDev *inst;
-    int64_t t;
+    const int64_t *tp;        // device step counter
+    int32_t dt;               // offset of this launch from *tp
+    int32_t meas_off;         // surface stage measures t - meas_off
+    int32_t red_off;          // reducer stage reduces t - red_off
     int32_t nseg;
     int32_t ntask;
-    SegInfo seg[kMaxSeg];
     int32_t n_red, n_sb;
-    int64_t t_red, t_meas;
+    int32_t pad;
+    SegInfo seg[kMaxSeg];
     const int32_t *sb_inst;   // per surface block: internal instance
     const int32_t *sb_chunk;  // per surface block: chunk of 64 elements
 };
@@ -179,7 +184,7 @@ __device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlan
 // with c = c(x) the local sound speed.
 // ---------------------------------------------------------------------------
 template <int DIM, typename S, int CPL, int XM, int NT>
-__device__ inline void lattice_task(const StepArgs &a, int task, int lane)
+__device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task, int lane)
 {
     using T = StoreTraits<S>;
     using R = typename T::R;
@@ -200,13 +205,13 @@ __device__ inline void lattice_task(const StepArgs &a, int task, int lane)
     const int y = r / sg.xsegs;
     const int xs = r - y * sg.xsegs;
     const InstDev &I = a.inst[sg.first + il];
-    if (I.max_steps > 0 && a.t >= I.max_steps) return;
+    if (I.max_steps > 0 && t >= I.max_steps) return;
 
     const int nx = sg.nx, ny = sg.ny, nz = sg.nz;
     const int pitch = I.pitch;
     const int64_t plane = I.plane;
-    const R *src = static_cast<const R *>(I.buf[a.t & 1]);
-    R *dst = static_cast<R *>(I.buf[(a.t + 1) & 1]);
+    const R *src = static_cast<const R *>(I.buf[t & 1]);
+    R *dst = static_cast<R *>(I.buf[(t + 1) & 1]);
     const bool driven = (I.xbc == 0);
     const int ym = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
@@ -300,7 +305,7 @@ __device__ inline void lattice_task(const StepArgs &a, int task, int lane)
                 const int by = y - I.mb_lo[1];
                 const int bz = (DIM == 3) ? z - I.mb_lo[2] : 0;
                 using V4 = typename VecT<C, 4>::type;
-                V4 *m = static_cast<V4 *>(I.mom[a.t & 1]) +
+                V4 *m = static_cast<V4 *>(I.mom[t & 1]) +
                         (((int64_t)bz * I.mb_n[1] + by) * I.mb_n[0] + bx);
                 V4 mv;
                 mv[0] = rho;
@@ -334,7 +339,7 @@ __device__ inline void lattice_task(const StepArgs &a, int task, int lane)
             }
         } else if (driven && x == 1) {
             // imposed density with the cell's own momentum (eq. imposingfields)
-            const C rs = (C)(I.src_amp * sin(I.omega * (double)a.t));
+            const C rs = (C)(I.src_amp * sin(I.omega * (double)t));
             const C h = (C)0.5;
             out[0] = rs * ((C)1 - (C)DIM * c2);
 #pragma unroll
@@ -372,7 +377,8 @@ __device__ inline void lattice_task(const StepArgs &a, int task, int lane)
 // summed over the 64 elements in a fixed order into one partial per chunk.
 // ---------------------------------------------------------------------------
 template <int DIM, typename C>
-__device__ inline void surface_block(const StepArgs &a, int sb, double (*lds)[64][4])
+__device__ inline void surface_block(const StepArgs &a, const int64_t t_meas, int sb,
+                                     double (*lds)[64][4])
 {
     constexpr int NN = (DIM == 3) ? 27 : 9;
     constexpr int PER = (NN + 3) / 4;
@@ -382,7 +388,7 @@ __device__ inline void surface_block(const StepArgs &a, int sb, double (*lds)[64
     const int chunk = a.sb_chunk[sb];
     const int k = chunk * 64 + lane;
     const bool live = k < I.n_surf;
-    const C *mom = static_cast<const C *>(I.mom[a.t_meas & 1]);
+    const C *mom = static_cast<const C *>(I.mom[t_meas & 1]);
     const int mbx = I.mb_n[0], mby = I.mb_n[1];
 
     double rI = 0.0, Jx = 0.0, Jy = 0.0, Jz = 0.0;
@@ -429,7 +435,7 @@ __device__ inline void surface_block(const StepArgs &a, int sb, double (*lds)[64
         fz += __shfl_xor(fz, off);
     }
     if (lane == 0) {
-        double *o = I.part + ((a.t_meas & 1) * I.n_chunks + chunk) * 4;
+        double *o = I.part + ((t_meas & 1) * I.n_chunks + chunk) * 4;
         o[0] = fx;
         o[1] = fy;
         o[2] = fz;
@@ -438,12 +444,11 @@ __device__ inline void surface_block(const StepArgs &a, int sb, double (*lds)[64
 
 // Reducer: F(t_red) of one instance from its chunk partials (written by the
 // previous launch), scaled, traced and accumulated.
-__device__ inline void reduce_block(const StepArgs &a, int ii)
+__device__ inline void reduce_block(const StepArgs &a, const int64_t t, int ii)
 {
     if (threadIdx.x != 0) return;
     const InstDev &I = a.inst[ii];
     if (I.n_surf == 0) return;
-    const int64_t t = a.t_red;
     if (I.max_steps > 0 && t >= I.max_steps) return;
     const double *p = I.part + (t & 1) * I.n_chunks * 4;
     double s0 = 0.0, s1 = 0.0, s2 = 0.0;
@@ -472,22 +477,34 @@ template <int DIM, typename S, int CPL, int XM, int NT>
 __global__ void __launch_bounds__(kStepThreads) step_kernel(StepArgs a)
 {
     __shared__ double lds[4][64][4];
+    const int64_t t = *a.tp + a.dt;
     const int b = blockIdx.x;
     if (b < a.n_red) {
-        reduce_block(a, b);
+        reduce_block(a, t - a.red_off, b);
         return;
     }
     if (b < a.n_red + a.n_sb) {
         const int sb = b - a.n_red;
         const InstDev &I = a.inst[a.sb_inst[sb]];
-        if (I.max_steps > 0 && a.t_meas >= I.max_steps) return;
-        surface_block<DIM, typename StoreTraits<S>::C>(a, sb, lds);
+        const int64_t t_meas = t - a.meas_off;
+        if (I.max_steps > 0 && t_meas >= I.max_steps) return;
+        surface_block<DIM, typename StoreTraits<S>::C>(a, t_meas, sb, lds);
         return;
     }
     const int wave = wave_uniform(threadIdx.x >> 6);
     const int task = (b - a.n_red - a.n_sb) * (kStepThreads / 64) + wave;
     if (task >= a.ntask) return;
-    lattice_task<DIM, S, CPL, XM, NT>(a, task, threadIdx.x & 63);
+    lattice_task<DIM, S, CPL, XM, NT>(a, t, task, threadIdx.x & 63);
+}
+
+// Device step counter: set, or advance after a replayed sequence.
+__global__ void set_step_kernel(int64_t *tp, int64_t v)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *tp = v;
+}
+__global__ void advance_step_kernel(int64_t *tp, int64_t k)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *tp = *tp + k;
 }
 
 // Fill with zeros (used instead of hipMemsetAsync so that every node of a

@@ -310,7 +310,7 @@ struct InstPlan {
 };
 
 struct Layout {
-    size_t off_inst, off_acc, off_sbtab, total;
+    size_t off_inst, off_acc, off_sbtab, off_tdev, total;
     int n_sb_total;
     std::vector<InstPlan> p;
 };
@@ -327,6 +327,8 @@ Layout plan(const lb_wave_desc *descs, int n)
     for (int i = 0; i < n; ++i) L.n_sb_total += (descs[i].n_surf + 63) / 64;
     L.off_sbtab = off;
     off = align_up(off + sizeof(int32_t) * 2 * (size_t)L.n_sb_total);
+    L.off_tdev = off;
+    off = align_up(off + sizeof(int64_t));
     L.p.resize(n);
     for (int i = 0; i < n; ++i) {
         const lb_wave_desc &d = descs[i];
@@ -424,6 +426,20 @@ struct lb_wave {
     int64_t meas = 0;                 // steps whose chunk partials exist
     int64_t red = 0;                  // steps reduced into the accumulators
     bool nan_seen = false;
+    int64_t *d_t = nullptr;           // device step counter
+    int64_t tdev = 0;                 // its value in stream order
+    int graph_chunk = 0;              // replay steady steps as captured graphs of this length
+    hipStream_t cap_stream = nullptr; // private stream used only for capture
+    struct GraphEntry {
+        int k, na, n_red, n_sb;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    ~lb_wave()
+    {
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.exec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
 };
 
 namespace {
@@ -462,87 +478,84 @@ void launch_t(const StepArgs &a, int blocks, hipStream_t st)
 // Variants compiled per storage: 16-bit storage only shifts across lanes (its
 // elements are 2 bytes, too small for the offset vector load).
 template <int DIM, typename S, int CPL>
-void launch_c(const lb_wave *h, const StepArgs &a, int blocks)
+void launch_c(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
 {
     constexpr bool wide = sizeof(typename StoreTraits<S>::R) >= 4;
     constexpr int XW = wide ? 1 : 0;
     if (h->xm == 1 && wide) {
         switch (h->nt) {
-        case 1: launch_t<DIM, S, CPL, XW, 1>(a, blocks, h->stream); break;
-        case 2: launch_t<DIM, S, CPL, XW, 2>(a, blocks, h->stream); break;
-        default: launch_t<DIM, S, CPL, XW, 0>(a, blocks, h->stream); break;
+        case 1: launch_t<DIM, S, CPL, XW, 1>(a, blocks, st); break;
+        case 2: launch_t<DIM, S, CPL, XW, 2>(a, blocks, st); break;
+        default: launch_t<DIM, S, CPL, XW, 0>(a, blocks, st); break;
         }
     } else {
         switch (h->nt) {
-        case 1: launch_t<DIM, S, CPL, 0, 1>(a, blocks, h->stream); break;
-        case 2: launch_t<DIM, S, CPL, 0, 2>(a, blocks, h->stream); break;
-        default: launch_t<DIM, S, CPL, 0, 0>(a, blocks, h->stream); break;
+        case 1: launch_t<DIM, S, CPL, 0, 1>(a, blocks, st); break;
+        case 2: launch_t<DIM, S, CPL, 0, 2>(a, blocks, st); break;
+        default: launch_t<DIM, S, CPL, 0, 0>(a, blocks, st); break;
         }
     }
 }
 
 template <int DIM, typename S>
-void launch_s(const lb_wave *h, const StepArgs &a, int blocks)
+void launch_s(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
 {
     switch (h->vx) {
-    case 2: launch_c<DIM, S, 2>(h, a, blocks); break;
-    case 4: launch_c<DIM, S, 4>(h, a, blocks); break;
-    default: launch_c<DIM, S, 1>(h, a, blocks); break;
+    case 2: launch_c<DIM, S, 2>(h, a, blocks, st); break;
+    case 4: launch_c<DIM, S, 4>(h, a, blocks, st); break;
+    default: launch_c<DIM, S, 1>(h, a, blocks, st); break;
     }
 }
 
-void launch(const lb_wave *h, const StepArgs &a, int blocks)
+void launch(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
 {
     if (blocks <= 0) return;
     const bool d2 = h->dim == 2;
     switch (h->storage) {
-    case LB_F64: d2 ? launch_s<2, double>(h, a, blocks) : launch_s<3, double>(h, a, blocks); break;
-    case LB_F32: d2 ? launch_s<2, float>(h, a, blocks) : launch_s<3, float>(h, a, blocks); break;
+    case LB_F64: d2 ? launch_s<2, double>(h, a, blocks, st) : launch_s<3, double>(h, a, blocks, st); break;
+    case LB_F32: d2 ? launch_s<2, float>(h, a, blocks, st) : launch_s<3, float>(h, a, blocks, st); break;
     case LB_F16:
-        d2 ? launch_s<2, _Float16>(h, a, blocks) : launch_s<3, _Float16>(h, a, blocks);
+        d2 ? launch_s<2, _Float16>(h, a, blocks, st) : launch_s<3, _Float16>(h, a, blocks, st);
         break;
-    default: d2 ? launch_s<2, bf16>(h, a, blocks) : launch_s<3, bf16>(h, a, blocks); break;
+    default: d2 ? launch_s<2, bf16>(h, a, blocks, st) : launch_s<3, bf16>(h, a, blocks, st); break;
     }
 }
 
-// Measurement part of a launch: partials of F(meas) if the newest state is
-// f^new(meas) and it has not been measured, reduction of F(red) if its
-// partials came from an earlier launch.  `newest` is the step whose f^new
-// the launch's lattice blocks read (t - 1), or the last completed step.
-void plan_measure(lb_wave *h, StepArgs &a, int64_t newest)
+// Measurement part of the launch for step t_launch: partials of F(t_launch - 1)
+// if that state's moments exist and it has not been measured, reduction of
+// the oldest measured step whose partials came from an earlier launch.
+void plan_measure(lb_wave *h, StepArgs &a, int64_t t_launch)
 {
     a.n_red = 0;
     a.n_sb = 0;
+    a.meas_off = 1;
+    a.red_off = 2;
+    a.sb_inst = h->d_sb_inst;
+    a.sb_chunk = h->d_sb_chunk;
     if (!h->any_surf) {
-        h->meas = h->red = newest + 1;
+        h->meas = h->red = t_launch;
         return;
     }
     if (h->red < h->meas) {
-        a.t_red = h->red;
+        a.red_off = (int32_t)(t_launch - h->red);
         a.n_red = prefix_alive(h, h->red);
         h->red++;
     }
+    const int64_t newest = t_launch - 1;
     if (newest >= 0 && h->meas == newest) {
-        a.t_meas = newest;
         a.n_sb = h->sb_first[prefix_alive(h, newest)];
         h->meas++;
     }
-    a.sb_inst = h->d_sb_inst;
-    a.sb_chunk = h->d_sb_chunk;
 }
 
-// One lattice step for every live instance, with the measurement of the
-// previous step's state folded into the same launch.
-int enqueue_step(lb_wave *h)
+// Fill the lattice part of `a` for step t (segments of the live prefix) and
+// launch, one launch per kMaxSeg segments; the measurement blocks ride on
+// the first launch.
+void emit_step(const lb_wave *h, StepArgs a, int64_t t, int32_t dt, hipStream_t st)
 {
-    const int64_t t = h->t;
     const int na = active_prefix(h, t);
     const int ntask_active = h->task0[na];
-    StepArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.inst = h->d_inst;
-    a.t = t;
-    plan_measure(h, a, t - 1);
+    a.dt = dt;
     size_t s = 0;
     bool first = true;
     do {
@@ -557,10 +570,33 @@ int enqueue_step(lb_wave *h)
         a.nseg = k;
         a.ntask = k > 0 ? end - base : 0;
         if (!first) a.n_red = a.n_sb = 0;
-        launch(h, a, a.n_red + a.n_sb + (a.ntask + 3) / 4);
+        launch(h, a, a.n_red + a.n_sb + (a.ntask + 3) / 4, st);
         first = false;
         s += k;
     } while (s < h->segs.size() && h->segs[s].task0 < ntask_active);
+}
+
+// Make the device counter equal `t` in stream order if dt would not fit.
+void sync_counter(lb_wave *h, int64_t t)
+{
+    if (t - h->tdev > (1 << 30) || t < h->tdev) {
+        hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, h->stream, h->d_t, t);
+        h->tdev = t;
+    }
+}
+
+// One lattice step for every live instance, with the measurement of the
+// previous steps folded into the same launch.
+int enqueue_step(lb_wave *h)
+{
+    const int64_t t = h->t;
+    sync_counter(h, t);
+    StepArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.inst = h->d_inst;
+    a.tp = h->d_t;
+    plan_measure(h, a, t);
+    emit_step(h, a, t, (int32_t)(t - h->tdev), h->stream);
     HIP_TRY(hipGetLastError());
     h->t++;
     return LB_OK;
@@ -570,15 +606,87 @@ int enqueue_step(lb_wave *h)
 int flush_measure(lb_wave *h)
 {
     while (h->red < h->t) {
+        sync_counter(h, h->t);
         StepArgs a;
         std::memset(&a, 0, sizeof a);
         a.inst = h->d_inst;
-        a.t = h->t;
-        plan_measure(h, a, h->t - 1);
-        launch(h, a, a.n_red + a.n_sb);
+        a.tp = h->d_t;
+        a.dt = (int32_t)(h->t - h->tdev);
+        plan_measure(h, a, h->t);
+        launch(h, a, a.n_red + a.n_sb, h->stream);
         HIP_TRY(hipGetLastError());
     }
     return LB_OK;
+}
+
+// Steps t .. t+k-1 all launch the same blocks: the measurement runs one and
+// two steps behind and no instance stops inside the window.
+bool steady(const lb_wave *h, int64_t k)
+{
+    const int64_t t = h->t;
+    if (h->any_surf && (t < 2 || h->meas != t - 1 || h->red != t - 2)) return false;
+    for (const InstDev &I : h->hinst) {
+        const int64_t ms = I.max_steps;
+        if (ms > 0 && ms > t - 2 && ms < t + k) return false;
+    }
+    return true;
+}
+
+// Replay k steady steps as one captured graph (captured once per launch
+// shape on a private stream, launched on the handle's stream).
+int replay_steps(lb_wave *h, int k)
+{
+    const int64_t t = h->t;
+    const int na = active_prefix(h, t);
+    const int n_red = h->any_surf ? prefix_alive(h, t - 2) : 0;
+    const int n_sb = h->any_surf ? h->sb_first[prefix_alive(h, t - 1)] : 0;
+    hipGraphExec_t exec = nullptr;
+    for (auto &g : h->graphs)
+        if (g.k == k && g.na == na && g.n_red == n_red && g.n_sb == n_sb) exec = g.exec;
+    if (!exec) {
+        if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+        HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        StepArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.inst = h->d_inst;
+        a.tp = h->d_t;
+        a.meas_off = 1;
+        a.red_off = 2;
+        a.n_red = n_red;
+        a.n_sb = n_sb;
+        a.sb_inst = h->d_sb_inst;
+        a.sb_chunk = h->d_sb_chunk;
+        for (int j = 0; j < k; ++j) emit_step(h, a, t + j, j, h->cap_stream);
+        hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, h->cap_stream, h->d_t,
+                           (int64_t)k);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(h->cap_stream, &graph);
+        if (e != hipSuccess) return fail(LB_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail(LB_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
+        h->graphs.push_back({k, na, n_red, n_sb, exec});
+    }
+    if (h->tdev != t) {
+        hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, h->stream, h->d_t, t);
+        h->tdev = t;
+    }
+    HIP_TRY(hipGraphLaunch(exec, h->stream));
+    h->t += k;
+    h->tdev += k;
+    if (h->any_surf) {
+        h->meas += k;
+        h->red += k;
+    } else {
+        h->meas = h->red = h->t;
+    }
+    return LB_OK;
+}
+
+void drop_graphs(lb_wave *h)
+{
+    for (auto &g : h->graphs) (void)hipGraphExecDestroy(g.exec);
+    h->graphs.clear();
 }
 
 int zero_region(lb_wave *h, size_t off, size_t bytes)
@@ -609,6 +717,8 @@ int zero_state(lb_wave *h)
     if (st) return st;
     h->t = h->meas = h->red = 0;
     h->nan_seen = false;
+    hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, h->stream, h->d_t, (int64_t)0);
+    h->tdev = 0;
     return LB_OK;
 }
 
@@ -668,6 +778,7 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
     h->d_acc = reinterpret_cast<AccDev *>(h->ws + L.off_acc);
     h->d_sb_inst = reinterpret_cast<int32_t *>(h->ws + L.off_sbtab);
     h->d_sb_chunk = h->d_sb_inst + L.n_sb_total;
+    h->d_t = reinterpret_cast<int64_t *>(h->ws + L.off_tdev);
     h->vx = 1;
 
     // internal order: longest runs first (so the active set is a prefix),
@@ -836,11 +947,29 @@ int lb_wave_step_n(lb_wave *h, int64_t n_steps)
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     if (n_steps < 0) return fail(LB_EINVAL, "n_steps < 0");
     if (h->nan_seen) return fail(LB_ENAN, "a previous force was not finite");
-    for (int64_t s = 0; s < n_steps; ++s) {
-        int st = enqueue_step(h);
+    int64_t left = n_steps;
+    while (left > 0) {
+        const int k = h->graph_chunk;
+        int st;
+        if (k >= 2 && left >= k && steady(h, k)) {
+            st = replay_steps(h, k);
+            left -= k;
+        } else {
+            st = enqueue_step(h);
+            left -= 1;
+        }
         if (st != LB_OK) return st;
     }
     return flush_measure(h);
+}
+
+int lb_wave_set_graph(lb_wave *h, int32_t chunk)
+{
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (chunk < 0 || chunk == 1 || chunk > 4096) return fail(LB_EINVAL, "chunk must be 0 or 2..4096");
+    if (chunk != h->graph_chunk) drop_graphs(h);
+    h->graph_chunk = chunk;
+    return LB_OK;
 }
 
 int lb_surface_force(lb_wave *h, double *F_avg, int64_t *n_accum)
@@ -973,7 +1102,8 @@ int lb_wave_set_variant(lb_wave *h, int32_t cells_per_lane, int32_t x_mode, int3
     if (x_mode == 1 && elem_bytes(h->storage) < 4)
         return fail(LB_EINVAL, "x_mode 1 needs 4- or 8-byte storage");
     if (nontemporal < 0 || nontemporal > 2) return fail(LB_EINVAL, "nontemporal must be 0, 1 or 2");
-    // the task table depends on the row tile width
+    // the task table and any captured sequence depend on the variant
+    drop_graphs(h);
     h->vx = cells_per_lane;
     h->xm = x_mode;
     h->nt = nontemporal;

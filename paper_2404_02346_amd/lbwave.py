@@ -78,6 +78,7 @@ def lib():
         L.lb_wave_get_variant.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                           C.POINTER(C.c_int32)]
         L.lb_wave_set_tile.argtypes = [vp, C.c_int32]
+        L.lb_wave_set_graph.argtypes = [vp, C.c_int32]
         L.lb_wave_get_tile.argtypes = [vp, C.POINTER(C.c_int32)]
         L.lb_wave_autotune.argtypes = [vp, C.c_int32, _dp]
         L.lb_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
@@ -254,6 +255,9 @@ class LBWave:
         a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
         _check(lib().lb_wave_get_variant(self._h, C.byref(a), C.byref(b), C.byref(c)))
         return a.value, b.value, c.value
+
+    def set_graph(self, chunk: int):
+        _check(lib().lb_wave_set_graph(self._h, int(chunk)))
 
     def tile(self) -> int:
         v = C.c_int32()

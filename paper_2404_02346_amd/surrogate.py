@@ -1,0 +1,324 @@
+"""MLP surrogate of the time-averaged radiation force, trained on batched LB runs.
+
+The network (include/lb_mlp.h; BF16 MFMA forward, backward and Adam kernels in
+csrc/lb_mlp.hip) maps (k R, k h, c_p/c0), each mapped linearly from the
+training box to [-1, 1], to F / F0 with F0 = pi R^3 Pa^2 k / (3 rho0 c0^2),
+the scale of the small-sphere force (eq. ARF_Gorkov_3D): F/F0 -> f1 sin 2kh
+as kR -> 0, f1 = 1 - c0^2/c_p^2 for a density-matched sphere.
+
+Training data come from the batched lattice Boltzmann runs (lbwave.LBWave
+with many uneven instances); the same LB stays the reference for the error
+and the fallback for queries outside the training box.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+
+import numpy as np
+
+from . import lbwave
+
+BOX = {"kR": (0.05, 0.6), "kh": (0.0, math.pi / 2), "ratio": (0.8, 1.5)}
+C0 = 1.0 / 3.0  # fluid sound speed of the batched boxes (keeps c_p <= 0.5 < 1/sqrt(3))
+
+_fp = C.POINTER(C.c_float)
+
+
+def _mlp_lib():
+    L = lbwave.lib()
+    if not getattr(L, "_mlp_ready", False):
+        vp = C.c_void_p
+        L.lb_mlp_num_params.restype = C.c_int32
+        L.lb_mlp_workspace_bytes.argtypes = [C.c_int32]
+        L.lb_mlp_workspace_bytes.restype = C.c_size_t
+        L.lb_mlp_create.argtypes = [C.c_int32, vp, C.c_size_t, vp, C.POINTER(vp)]
+        L.lb_mlp_destroy.argtypes = [vp]
+        L.lb_mlp_set_params.argtypes = [vp, _fp]
+        L.lb_mlp_get_params.argtypes = [vp, _fp]
+        L.lb_mlp_forward.argtypes = [vp, vp, C.c_int32, vp]
+        L.lb_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, _fp, C.POINTER(C.c_double)]
+        L.lb_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                        C.c_float]
+        L.lb_mlp_last_loss.argtypes = [vp, C.POINTER(C.c_double)]
+        L.lb_mlp_mfma_probe.argtypes = [vp, vp, vp, vp]
+        L._mlp_ready = True
+    return L
+
+
+def num_params() -> int:
+    return int(_mlp_lib().lb_mlp_num_params())
+
+
+DIMS = (3, 256, 256, 256, 256, 1)
+
+
+def init_params(seed: int) -> np.ndarray:
+    """Seeded initial parameters: W ~ N(0, 2/fan_in) (GELU layers), last layer N(0, 1/fan_in), b = 0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for i in range(len(DIMS) - 1):
+        n, k = DIMS[i + 1], DIMS[i]
+        std = math.sqrt((2.0 if i < len(DIMS) - 2 else 1.0) / k)
+        out.append(rng.normal(0.0, std, size=n * k))
+        out.append(np.zeros(n))
+    return np.concatenate(out).astype(np.float32)
+
+
+def normalize(kR, kh, ratio) -> np.ndarray:
+    """Map (kR, kh, c_p/c0) from the training box to [-1, 1]^3 (B x 3 float32)."""
+    cols = []
+    for v, key in ((kR, "kR"), (kh, "kh"), (ratio, "ratio")):
+        lo, hi = BOX[key]
+        cols.append(2.0 * (np.asarray(v, dtype=np.float64) - lo) / (hi - lo) - 1.0)
+    return np.stack(cols, axis=-1).astype(np.float32).reshape(-1, 3)
+
+
+def in_box(kR, kh, ratio) -> np.ndarray:
+    ok = np.ones(np.broadcast(np.asarray(kR), np.asarray(kh), np.asarray(ratio)).shape, bool)
+    for v, key in ((kR, "kR"), (kh, "kh"), (ratio, "ratio")):
+        lo, hi = BOX[key]
+        v = np.asarray(v)
+        ok &= (v >= lo) & (v <= hi)
+    return ok
+
+
+class MLP:
+    """Handle on the GPU network (lb_mlp_create) with a torch workspace and stream."""
+
+    def __init__(self, max_batch: int = 4096, params=None, seed: int = 0, stream=None):
+        import torch
+        L = _mlp_lib()
+        self.max_batch = int(max_batch)
+        nb = L.lb_mlp_workspace_bytes(self.max_batch)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self._h = C.c_void_p()
+        lbwave._check(L.lb_mlp_create(self.max_batch, C.c_void_p(self.ws.data_ptr()), nb,
+                                      C.c_void_p(self.stream.cuda_stream), C.byref(self._h)))
+        self.set_params(init_params(seed) if params is None else params)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _mlp_lib().lb_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(np.asarray(p, dtype=np.float32))
+        assert a.size == num_params()
+        lbwave._check(_mlp_lib().lb_mlp_set_params(self._h, a.ctypes.data_as(_fp)))
+
+    def params(self) -> np.ndarray:
+        out = np.empty(num_params(), dtype=np.float32)
+        lbwave._check(_mlp_lib().lb_mlp_get_params(self._h, out.ctypes.data_as(_fp)))
+        return out
+
+    def _dev(self, a, cols=None):
+        import torch
+        t = torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float32)), device="cuda")
+        return t if cols is None else t.reshape(-1, cols)
+
+    def forward_dev(self, x_dev, y_dev, B: int):
+        lbwave._check(_mlp_lib().lb_mlp_forward(self._h, C.c_void_p(x_dev.data_ptr()), int(B),
+                                                C.c_void_p(y_dev.data_ptr())))
+
+    def predict(self, x) -> np.ndarray:
+        import torch
+        x = np.asarray(x, dtype=np.float32).reshape(-1, 3)
+        out = np.empty(len(x), dtype=np.float32)
+        for s in range(0, len(x), self.max_batch):
+            xb = self._dev(x[s: s + self.max_batch], 3)
+            yb = torch.empty(len(xb), dtype=torch.float32, device="cuda")
+            self.forward_dev(xb, yb, len(xb))
+            out[s: s + len(xb)] = yb.cpu().numpy()
+        return out
+
+    def grad(self, x, t):
+        x_d, t_d = self._dev(x, 3), self._dev(t)
+        g = np.empty(num_params(), dtype=np.float32)
+        loss = C.c_double()
+        lbwave._check(_mlp_lib().lb_mlp_grad(self._h, C.c_void_p(x_d.data_ptr()),
+                                             C.c_void_p(t_d.data_ptr()), len(t_d),
+                                             g.ctypes.data_as(_fp), C.byref(loss)))
+        return loss.value, g
+
+    def train(self, x, t, steps: int, lr: float = 1e-3, batch: int | None = None, seed: int = 0,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, lr_final: float = None,
+              log_every: int = 0):
+        """Adam on the mean squared error; mini-batches drawn with a seeded permutation."""
+        import torch
+        x = np.asarray(x, dtype=np.float32).reshape(-1, 3)
+        t = np.asarray(t, dtype=np.float32).reshape(-1)
+        n = len(t)
+        batch = min(batch or n, self.max_batch, n)
+        x_d, t_d = self._dev(x, 3), self._dev(t)
+        rng = np.random.Generator(np.random.PCG64(seed))
+        L = _mlp_lib()
+        losses = []
+        order = rng.permutation(n)
+        pos = 0
+        for s in range(steps):
+            if batch == n:
+                xb, tb = x_d, t_d
+            else:
+                if pos + batch > n:
+                    order, pos = rng.permutation(n), 0
+                idx = torch.as_tensor(order[pos: pos + batch], device="cuda")
+                pos += batch
+                xb, tb = x_d[idx].contiguous(), t_d[idx].contiguous()
+            cur = lr if lr_final is None else lr * (lr_final / lr) ** (s / max(steps - 1, 1))
+            lbwave._check(L.lb_mlp_train_step(self._h, C.c_void_p(xb.data_ptr()),
+                                              C.c_void_p(tb.data_ptr()), len(tb), cur, beta1,
+                                              beta2, eps))
+            if log_every and (s % log_every == 0 or s == steps - 1):
+                v = C.c_double()
+                lbwave._check(L.lb_mlp_last_loss(self._h, C.byref(v)))
+                losses.append((s, v.value))
+        return losses
+
+
+def mfma_probe(A_bits: np.ndarray, B_bits: np.ndarray) -> np.ndarray:
+    """One 16x16x32 BF16 MFMA tile through the library (lane-layout check)."""
+    import torch
+    a = torch.as_tensor(np.ascontiguousarray(A_bits.astype(np.int16)), device="cuda")
+    b = torch.as_tensor(np.ascontiguousarray(B_bits.astype(np.int16)), device="cuda")
+    d = torch.zeros(256, dtype=torch.float32, device="cuda")
+    s = torch.cuda.current_stream()
+    lbwave._check(_mlp_lib().lb_mlp_mfma_probe(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                               C.c_void_p(d.data_ptr()),
+                                               C.c_void_p(s.cuda_stream)))
+    return d.cpu().numpy().reshape(16, 16)
+
+
+# ---------------------------------------------------------------------------
+# Training data from batched LB runs
+# ---------------------------------------------------------------------------
+
+def calibrate_edges(edges, c0: float = C0):
+    """GPU cavity calibration per box edge (lambda = edge): antinode, wavenumber, Pa."""
+    out = {}
+    for e in edges:
+        cal = lbwave.cavity_calibrate(int(e), c0, 2 * math.pi * c0 / e)
+        out[int(e)] = cal
+    return out
+
+
+def force_scale(R, Pa, lam, c0: float = C0, rho0: float = 1.0):
+    """F0 = pi R^3 Pa^2 k / (3 rho0 c0^2) with k = 2 pi / lambda."""
+    k = 2 * math.pi / lam
+    return math.pi * R ** 3 * Pa ** 2 * k / (3 * rho0 * c0 ** 2)
+
+
+def run_batch(problems, storage: str = "f32", autotune: bool = True, stream=None,
+              graph: int = 64):
+    """Run uneven instances in one handle to their own lengths; returns forces and timing."""
+    import time
+
+    import torch
+    h = lbwave.LBWave(problems, storage=storage, stream=stream, freeze_at_n_steps=True)
+    tune = None
+    if autotune:
+        tune = h.autotune(2)
+    h.set_graph(graph)
+    n = max(int(p["n_steps"]) for p in problems)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    h.step(n)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    F, nacc = h.force()
+    variant = h.variant()
+    h.close()
+    updates = sum(int(p["nx"]) * int(p["ny"]) * int(p["nz"]) * int(p["n_steps"]) for p in problems)
+    return {"F": F, "n_acc": nacc, "seconds": dt, "updates": updates, "variant": variant,
+            "autotune_ms": tune}
+
+
+def generate(seed: int, n: int, cal=None, kr_max: float = 0.6, storage: str = "f32",
+             chunk: int = 256, n_periods: int = 30, avg_periods: int = 10):
+    """Seeded samples of the batch generator (k R <= kr_max) with their LB forces."""
+    import workloads
+    cal = cal or calibrate_edges(workloads.BATCH_EDGES)
+    x_mid = {e: c["x_mid"] for e, c in cal.items()}
+    kk = {e: c["k"] for e, c in cal.items()}
+    probs, info = workloads.batch(seed, n, x_mid, kk, kr_max=kr_max, n_periods=n_periods,
+                                  avg_periods=avg_periods, return_draws=True)
+    rows, secs, upd = [], 0.0, 0
+    for s in range(0, n, chunk):
+        part = probs[s: s + chunk]
+        r = run_batch(part, storage=storage)
+        secs += r["seconds"]
+        upd += r["updates"]
+        print(f"batch {s // chunk}: {len(part)} instances, {r['updates']:.3e} updates in "
+              f"{r['seconds']:.1f} s, variant {r['variant']}", flush=True)
+        for p, F in zip(part, r["F"]):
+            lam = p["lam"]
+            R = p["radius"]
+            F0 = force_scale(R, cal[int(p["nx"])]["Pa"], lam)
+            rows.append({"edge": int(p["nx"]), "R": R, "ratio": p["cp_ratio"], "kh": p["kh"],
+                         "kR": 2 * math.pi * R / lam, "F": [float(v) for v in F],
+                         "F_over_F0": float(F[0] / F0)})
+    return {"seed": seed, "n": n, "kr_max": kr_max, "storage": storage, "rows": rows,
+            "rejected_draws": info["rejected"], "lb_seconds": secs, "lb_updates": upd}
+
+
+def table(data):
+    kR = np.array([r["kR"] for r in data["rows"]])
+    kh = np.array([r["kh"] for r in data["rows"]])
+    ratio = np.array([r["ratio"] for r in data["rows"]])
+    y = np.array([r["F_over_F0"] for r in data["rows"]])
+    return kR, kh, ratio, y
+
+
+def closed_form_ratio(kh, ratio):
+    """Small-sphere limit of F/F0 for a density-matched sphere: f1 sin 2kh, f1 = 1 - 1/ratio^2."""
+    return (1.0 - 1.0 / np.asarray(ratio) ** 2) * np.sin(2 * np.asarray(kh))
+
+
+def error_metric(pred, ref):
+    """max |pred - ref| / max |ref| over the set, and its RMS counterpart."""
+    pred, ref = np.asarray(pred), np.asarray(ref)
+    scale = np.abs(ref).max()
+    e = np.abs(pred - ref) / scale
+    return {"max": float(e.max()), "rms": float(np.sqrt(np.mean(e ** 2)))}
+
+
+class Surrogate:
+    """Trained network with the plain LB as fallback outside the training box."""
+
+    def __init__(self, mlp: MLP, lb_edge: int = 128, cal=None):
+        self.mlp = mlp
+        self.lb_edge = lb_edge
+        self.cal = cal
+
+    def predict(self, kR, kh, ratio):
+        """F/F0 for each query; LB runs for the queries outside the box."""
+        import workloads
+        kR, kh, ratio = (np.atleast_1d(np.asarray(v, dtype=np.float64)) for v in (kR, kh, ratio))
+        ok = in_box(kR, kh, ratio)
+        out = np.empty(kR.shape)
+        if ok.any():
+            out[ok] = self.mlp.predict(normalize(kR[ok], kh[ok], ratio[ok]))
+        bad = np.where(~ok)[0]
+        if len(bad):
+            e = self.lb_edge
+            if self.cal is None or e not in self.cal:
+                self.cal = calibrate_edges([e])
+            c = self.cal[e]
+            probs = []
+            for i in bad:
+                R = kR[i] * e / (2 * math.pi)
+                p = workloads.sphere_3d(c["x_mid"], c["k"], float(kh[i]), shape=(e, e, e),
+                                        lam=float(e), R=float(R), cp_ratio=float(ratio[i]),
+                                        n_surf=2048, c0=C0)
+                probs.append(p)
+            r = run_batch(probs, autotune=False)
+            for j, i in enumerate(bad):
+                out[i] = r["F"][j, 0] / force_scale(probs[j]["radius"], c["Pa"], float(e))
+        return out, ~ok

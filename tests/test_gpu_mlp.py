@@ -1,0 +1,119 @@
+"""GPU tests of the surrogate network kernels against the FP64 oracle.
+
+The GPU rounds weights, activations and back-propagated errors to BF16 and
+accumulates in FP32 on MFMA; the oracle is FP64 with the same BF16-rounded
+weights and inputs.  Bounds: relative 2-norm error 2e-2 for outputs and for
+each layer's gradient (a few BF16 roundings, 2^-8 relative each, through five
+layers).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mlp_oracle as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_02346_amd import surrogate as S
+    return S
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _bf16_bits(a):
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b))
+
+
+def test_mfma_tile_layout(S):
+    rng = np.random.Generator(np.random.PCG64(5))
+    A = M.bf16_round(rng.normal(size=(16, 32)))
+    B = M.bf16_round(rng.normal(size=(32, 16)))
+    D = S.mfma_probe(_bf16_bits(A), _bf16_bits(B))
+    np.testing.assert_allclose(D, A @ B, rtol=1e-5, atol=1e-5)
+
+
+def _layers(params):
+    return M.unpack(params)
+
+
+def test_forward_matches_oracle(S):
+    p = S.init_params(11)
+    rng = np.random.Generator(np.random.PCG64(12))
+    x = rng.uniform(-1, 1, size=(300, 3)).astype(np.float32)
+    net = S.MLP(max_batch=512, params=p)
+    y = net.predict(x)
+    ref, _ = M.forward(M.bf16_round(p), M.bf16_round(x))
+    e = _rel(y, ref)
+    say(f"forward rel err {e:.3e}")
+    assert e < 2e-2
+    net.close()
+
+
+def test_gradients_match_oracle(S):
+    p = S.init_params(13)
+    rng = np.random.Generator(np.random.PCG64(14))
+    x = rng.uniform(-1, 1, size=(257, 3)).astype(np.float32)
+    t = np.sin(2 * x[:, 1]) * x[:, 2]
+    net = S.MLP(max_batch=512, params=p)
+    loss, g = net.grad(x, t)
+    # biases enter in FP32 on the GPU: the oracle uses the BF16-rounded weights, FP32 biases
+    pr = p.astype(np.float64).copy()
+    off = 0
+    for i in range(len(M.DIMS) - 1):
+        n, k = M.DIMS[i + 1], M.DIMS[i]
+        pr[off: off + n * k] = M.bf16_round(pr[off: off + n * k])
+        off += n * k + n
+    lref, gref = M.loss_and_grad(pr, M.bf16_round(x), t.astype(np.float32))
+    say(f"loss gpu {loss:.6e} oracle {lref:.6e}")
+    assert loss == pytest.approx(lref, rel=2e-2)
+    off = 0
+    for i in range(len(M.DIMS) - 1):
+        n, k = M.DIMS[i + 1], M.DIMS[i]
+        ew = _rel(g[off: off + n * k], gref[off: off + n * k])
+        eb = _rel(g[off + n * k: off + n * k + n], gref[off + n * k: off + n * k + n])
+        say(f"  layer {i}: dW rel {ew:.3e} db rel {eb:.3e}")
+        assert ew < 2e-2 and eb < 2e-2
+        off += n * k + n
+    net.close()
+
+
+def test_training_fits_a_smooth_target(S):
+    rng = np.random.Generator(np.random.PCG64(21))
+    kR = rng.uniform(0.05, 0.6, 1024)
+    kh = rng.uniform(0, math.pi / 2, 1024)
+    ratio = rng.uniform(0.8, 1.5, 1024)
+    x = S.normalize(kR, kh, ratio)
+    t = S.closed_form_ratio(kh, ratio) * (1 - 0.3 * kR ** 2)
+    net = S.MLP(max_batch=1024, seed=3)
+    log = net.train(x, t, steps=2000, lr=3e-3, lr_final=1e-4, log_every=250)
+    say("loss curve", log)
+    assert log[-1][1] < 1e-3 * log[0][1]
+    pred = net.predict(x)
+    err = S.error_metric(pred, t)
+    say("fit error", err)
+    assert err["max"] < 0.05 and err["rms"] < 0.01
+    net.close()
+
+
+def test_batch_limits(S):
+    import paper_2404_02346_amd as P
+    net = S.MLP(max_batch=16)
+    with pytest.raises(P.LBError):
+        net.grad(np.zeros((17, 3)), np.zeros(17))
+    assert len(net.predict(np.zeros((40, 3)))) == 40  # predict splits into max_batch chunks
+    net.close()

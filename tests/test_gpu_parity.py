@@ -228,6 +228,37 @@ def test_sixteen_bit_variants_agree(P):
         h.close()
 
 
+def test_graph_replay_is_bitwise_identical(P):
+    # captured sequences of steps replayed at any step give the same bits as
+    # launching step by step, across measurement start-up, flushes and
+    # instances that stop inside the run
+    probs = []
+    for i, (shape, ms) in enumerate([((8, 10, 70), 0), ((6, 8, 64), 29), ((8, 10, 70), 51),
+                                     ((6, 8, 64), 12)]):
+        p = driven_object(3, shape, R=2.0, n_surf=80, avg_start=4)
+        p["max_steps"] = ms
+        probs.append(p)
+    say("graph replay vs direct launches")
+    outs = []
+    for chunk in (0, 8, 5, 64):
+        h = P.LBWave(probs, storage="f32", trace_steps=80)
+        h.set_graph(chunk)
+        h.step(37)
+        h.step(3)
+        h.step(40)
+        st = [h.get_state(i) for i in range(len(probs))]
+        tr = [h.trace(i, 80) for i in range(len(probs))]
+        F, nacc = h.force()
+        outs.append((st, tr, F, nacc))
+        h.close()
+    for o in outs[1:]:
+        for a, b in zip(o[0], outs[0][0]):
+            assert np.array_equal(a, b)
+        for a, b in zip(o[1], outs[0][1]):
+            assert np.array_equal(a, b)
+        assert np.array_equal(o[2], outs[0][2]) and np.array_equal(o[3], outs[0][3])
+
+
 def test_autotune_keeps_results(P):
     p = driven_object(3, (16, 32, 96), R=4.0, n_surf=300, avg_start=2)
     say("autotune")
