@@ -63,6 +63,42 @@ template <typename R> struct VecT<R, 1> {
     using type = R;
 };
 
+// Pointers into global memory (address space 1): loads and stores through
+// them take a uniform 64-bit base in scalar registers plus a 32-bit lane
+// offset, instead of flat accesses with per-lane 64-bit addresses.
+template <typename T> using gptr = T __attribute__((address_space(1))) *;
+template <typename T> __device__ inline gptr<T> to_global(void *p) { return (gptr<T>)p; }
+template <typename T> __device__ inline gptr<const T> to_global(const void *p)
+{
+    return (gptr<const T>)p;
+}
+
+// base + i elements with a 32-bit byte offset (i * sizeof(T) < 2^32 for any
+// row offset here), so the access can use a scalar base and a 32-bit offset.
+template <typename T> __device__ inline gptr<const T> at(gptr<const T> base, uint32_t i)
+{
+    return (gptr<const T>)((gptr<const char>)base + i * (uint32_t)sizeof(T));
+}
+template <typename T> __device__ inline gptr<T> at(gptr<T> base, uint32_t i)
+{
+    return (gptr<T>)((gptr<char>)base + i * (uint32_t)sizeof(T));
+}
+
+// The per-instance records do not change during a launch: reading them
+// through the constant address space lets them live in scalar registers.
+template <typename T> using cptr = const T __attribute__((address_space(4))) *;
+template <typename T> __device__ inline cptr<T> to_const(const T *p) { return (cptr<T>)p; }
+
+template <typename V, bool NT> __device__ inline V vload(gptr<const V> p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <typename V, bool NT> __device__ inline void vstore(gptr<V> p, V v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 template <typename V, bool NT> __device__ inline V vload(const V *p)
 {
     if constexpr (NT) return __builtin_nontemporal_load(p);
@@ -204,48 +240,66 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task
     r -= z * (sg.ny * sg.xsegs);
     const int y = r / sg.xsegs;
     const int xs = r - y * sg.xsegs;
-    const InstDev &I = a.inst[sg.first + il];
+    const auto &I = to_const(a.inst)[sg.first + il];
     if (I.max_steps > 0 && t >= I.max_steps) return;
 
+    // per-instance constants, read once before the population loads
     const int nx = sg.nx, ny = sg.ny, nz = sg.nz;
     const int pitch = I.pitch;
     const int64_t plane = I.plane;
-    const R *src = static_cast<const R *>(I.buf[t & 1]);
-    R *dst = static_cast<R *>(I.buf[(t + 1) & 1]);
     const bool driven = (I.xbc == 0);
+    const C c0sq = (C)I.c0sq;
+    const int bb_lo0 = I.bb_lo[0], bb_lo1 = I.bb_lo[1], bb_lo2 = I.bb_lo[2];
+    const int bb_n0 = I.bb_n[0], bb_n1 = I.bb_n[1], bb_n2 = I.bb_n[2];
+    const int mb_lo0 = I.mb_lo[0], mb_lo1 = I.mb_lo[1], mb_lo2 = I.mb_lo[2];
+    const int mb_n0 = I.mb_n[0], mb_n1 = I.mb_n[1], mb_n2 = I.mb_n[2];
+    const gptr<const C> c2box = to_global<C>(I.c2box);
+    const gptr<C> mom = to_global<C>(I.mom[t & 1]);
+    const C phi = (C)I.wall_phi;
+    const double src_amp = I.src_amp, omega = I.omega;
+    const gptr<const R> src = to_global<R>(static_cast<const void *>(I.buf[t & 1]));
+    const gptr<R> dst = to_global<R>(I.buf[(t + 1) & 1]);
+
     const int ym = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
     const int zm = (z == 0) ? nz - 1 : z - 1;
     const int zp = (z == nz - 1) ? 0 : z + 1;
     const int64_t row = ((int64_t)z * ny + y) * pitch;
-    const int64_t row_ym = ((int64_t)z * ny + ym) * pitch;
-    const int64_t row_yp = ((int64_t)z * ny + yp) * pitch;
-    const int64_t row_zm = ((int64_t)zm * ny + y) * pitch;
-    const int64_t row_zp = ((int64_t)zp * ny + y) * pitch;
+    // uniform row bases of the seven pulled populations
+    const gptr<const R> r0 = src + row;
+    const gptr<const R> r1 = src + plane + row;
+    const gptr<const R> r2 = src + 2 * plane + row;
+    const gptr<const R> r3 = src + 3 * plane + ((int64_t)z * ny + ym) * pitch;
+    const gptr<const R> r4 = src + 4 * plane + ((int64_t)z * ny + yp) * pitch;
+    const gptr<const R> r5 = src + 5 * plane + ((int64_t)zm * ny + y) * pitch;
+    const gptr<const R> r6 = src + 6 * plane + ((int64_t)zp * ny + y) * pitch;
 
     const int x0 = xs * 64 * CPL;
     const int xl = x0 + lane * CPL;
-    const bool lane_in = xl < pitch;  // the vector lies inside the row (cells >= nx are padding)
+    const uint32_t ux = (uint32_t)xl;  // unsigned lane offset: uniform base + 32-bit offset
+    // the lane owns at least one real cell (the vector then lies inside the
+    // row; cells >= nx of a straddling vector are padding)
+    const bool lane_in = xl < nx;
 
     C f[Q][CPL];
     {
         V v[Q];
         if (lane_in) {
-            v[0] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + row + xl));
+            v[0] = vload<V, (NT == 2)>((gptr<const V>)at(r0, ux));
             if (XM == 0) {
-                v[1] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + plane + row + xl));
-                v[2] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 2 * plane + row + xl));
+                v[1] = vload<V, (NT == 2)>((gptr<const V>)at(r1, ux));
+                v[2] = vload<V, (NT == 2)>((gptr<const V>)at(r2, ux));
             } else {
                 // one element earlier / later: stays inside the buffer because the
                 // +x plane follows plane 0 and the -x plane precedes plane 3
-                v[1] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + plane + row + xl - 1));
-                v[2] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 2 * plane + row + xl + 1));
+                v[1] = vload<V, (NT == 2)>((gptr<const V>)at(r1 - 1, ux));
+                v[2] = vload<V, (NT == 2)>((gptr<const V>)at(r2 + 1, ux));
             }
-            v[3] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 3 * plane + row_ym + xl));
-            v[4] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 4 * plane + row_yp + xl));
+            v[3] = vload<V, (NT == 2)>((gptr<const V>)at(r3, ux));
+            v[4] = vload<V, (NT == 2)>((gptr<const V>)at(r4, ux));
             if (DIM == 3) {
-                v[5] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 5 * plane + row_zm + xl));
-                v[6] = vload<V, (NT == 2)>(reinterpret_cast<const V *>(src + 6 * plane + row_zp + xl));
+                v[5] = vload<V, (NT == 2)>((gptr<const V>)at(r5, ux));
+                v[6] = vload<V, (NT == 2)>((gptr<const V>)at(r6, ux));
             }
         } else {
 #pragma unroll
@@ -266,30 +320,27 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task
         for (int c = 0; c < CPL - 1; ++c) f[2][c] = f[2][c + 1];
         f[1][0] = from_left;
         f[2][CPL - 1] = from_right;
-        if (lane == 0 && x0 > 0) f[1][0] = T::to_c(src[plane + row + x0 - 1]);
+        if (lane == 0 && x0 > 0) f[1][0] = T::to_c(r1[x0 - 1]);
         if (lane == 63) {
             const int xn = x0 + 64 * CPL;
-            f[2][CPL - 1] = (xn < nx) ? T::to_c(src[2 * plane + row + xn]) : C(0);
+            f[2][CPL - 1] = (xn < nx) ? T::to_c(r2[xn]) : C(0);
         }
     }
     // the two ends of the row: nothing enters from outside (driven) or wrap (periodic)
-    if (xl == 0) f[1][0] = driven ? C(0) : T::to_c(src[plane + row + nx - 1]);
+    if (xl == 0) f[1][0] = driven ? C(0) : T::to_c(r1[nx - 1]);
     {
         const int cl = nx - 1 - xl;
         if (cl >= 0 && cl < CPL) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c)
-                if (c == cl) f[2][c] = driven ? C(0) : T::to_c(src[2 * plane + row]);
+                if (c == cl) f[2][c] = driven ? C(0) : T::to_c(r2[0]);
         }
     }
 
-    const C c0sq = (C)I.c0sq;
-    const bool in_box_yz = (I.bb_n[0] > 0) && (y >= I.bb_lo[1]) && (y < I.bb_lo[1] + I.bb_n[1]) &&
-                           (DIM == 2 || ((z >= I.bb_lo[2]) && (z < I.bb_lo[2] + I.bb_n[2])));
-    const C *c2box = static_cast<const C *>(I.c2box);
-    const bool in_mbox_yz = (I.mb_n[0] > 0) && (y >= I.mb_lo[1]) &&
-                            (y < I.mb_lo[1] + I.mb_n[1]) &&
-                            (DIM == 2 || ((z >= I.mb_lo[2]) && (z < I.mb_lo[2] + I.mb_n[2])));
+    const bool in_box_yz = (bb_n0 > 0) && (y >= bb_lo1) && (y < bb_lo1 + bb_n1) &&
+                           (DIM == 2 || ((z >= bb_lo2) && (z < bb_lo2 + bb_n2)));
+    const bool in_mbox_yz = (mb_n0 > 0) && (y >= mb_lo1) && (y < mb_lo1 + mb_n1) &&
+                            (DIM == 2 || ((z >= mb_lo2) && (z < mb_lo2 + mb_n2)));
 
     V o[Q];
 #pragma unroll
@@ -300,28 +351,26 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task
         for (int i = 1; i < Q; ++i) rho += f[i][c];
         if (in_mbox_yz) {
             // rho1, J1 of the advected populations f(t) for the surface measurement
-            const int bx = x - I.mb_lo[0];
-            if (bx >= 0 && bx < I.mb_n[0] && x < nx) {
-                const int by = y - I.mb_lo[1];
-                const int bz = (DIM == 3) ? z - I.mb_lo[2] : 0;
+            const int bx = x - mb_lo0;
+            if (bx >= 0 && bx < mb_n0 && x < nx) {
+                const int by = y - mb_lo1;
+                const int bz = (DIM == 3) ? z - mb_lo2 : 0;
                 using V4 = typename VecT<C, 4>::type;
-                V4 *m = static_cast<V4 *>(I.mom[t & 1]) +
-                        (((int64_t)bz * I.mb_n[1] + by) * I.mb_n[0] + bx);
                 V4 mv;
                 mv[0] = rho;
                 mv[1] = f[1][c] - f[2][c];
                 mv[2] = f[3][c] - f[4][c];
                 mv[3] = (DIM == 3) ? f[5][c] - f[6][c] : C(0);
-                *m = mv;
+                *(gptr<V4>)(mom + 4 * (((int64_t)bz * mb_n1 + by) * mb_n0 + bx)) = mv;
             }
         }
         C c2 = c0sq;
         if (in_box_yz) {
-            const int bx = x - I.bb_lo[0];
-            if (bx >= 0 && bx < I.bb_n[0]) {
-                const int by = y - I.bb_lo[1];
-                const int bz = (DIM == 3) ? z - I.bb_lo[2] : 0;
-                c2 = c2box[((int64_t)bz * I.bb_n[1] + by) * I.bb_n[0] + bx];
+            const int bx = x - bb_lo0;
+            if (bx >= 0 && bx < bb_n0) {
+                const int by = y - bb_lo1;
+                const int bz = (DIM == 3) ? z - bb_lo2 : 0;
+                c2 = c2box[((int64_t)bz * bb_n1 + by) * bb_n0 + bx];
             }
         }
         C out[Q];
@@ -330,7 +379,6 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task
             for (int i = 0; i < Q; ++i) out[i] = C(0);  // padding stays zero
         } else if (driven && (x == 0 || x == nx - 1)) {
             // damped bounce-back of the pre-collision populations (eq. bounce-back)
-            const C phi = (C)I.wall_phi;
             out[0] = phi * f[0][c];
 #pragma unroll
             for (int i = 1; i < Q; i += 2) {
@@ -339,7 +387,7 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task
             }
         } else if (driven && x == 1) {
             // imposed density with the cell's own momentum (eq. imposingfields)
-            const C rs = (C)(I.src_amp * sin(I.omega * (double)t));
+            const C rs = (C)(src_amp * sin(omega * (double)t));
             const C h = (C)0.5;
             out[0] = rs * ((C)1 - (C)DIM * c2);
 #pragma unroll
@@ -363,7 +411,7 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task
     if (lane_in) {
 #pragma unroll
         for (int i = 0; i < Q; ++i)
-            vstore<V, (NT >= 1)>(reinterpret_cast<V *>(dst + i * plane + row + xl), o[i]);
+            vstore<V, (NT >= 1)>((gptr<V>)at(dst + (i * plane + row), ux), o[i]);
     }
 }
 
@@ -388,7 +436,7 @@ __device__ inline void surface_block(const StepArgs &a, const int64_t t_meas, in
     const int chunk = a.sb_chunk[sb];
     const int k = chunk * 64 + lane;
     const bool live = k < I.n_surf;
-    const C *mom = static_cast<const C *>(I.mom[t_meas & 1]);
+    const gptr<const C> mom = to_global<C>(static_cast<const void *>(I.mom[t_meas & 1]));
     const int mbx = I.mb_n[0], mby = I.mb_n[1];
 
     double rI = 0.0, Jx = 0.0, Jy = 0.0, Jz = 0.0;
@@ -399,7 +447,8 @@ __device__ inline void surface_block(const StepArgs &a, const int64_t t_meas, in
             const int n = w + 4 * j;
             if (n < NN) {
                 const int dx = n % 3, dy = (n / 3) % 3, dz = n / 9;
-                const C *m = mom + 4 * (((int64_t)P.bz[dz] * mby + P.by[dy]) * mbx + P.bx[dx]);
+                const gptr<const C> m =
+                    mom + 4 * (((int64_t)P.bz[dz] * mby + P.by[dy]) * mbx + P.bx[dx]);
                 const double wt = P.w[dx] * P.w[3 + dy] * P.w[6 + dz];
                 rI += wt * (double)m[0];
                 Jx += wt * (double)m[1];

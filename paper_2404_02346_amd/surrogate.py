@@ -19,7 +19,11 @@ import numpy as np
 
 from . import lbwave
 
+# input box mapped to [-1, 1] (the network's nominal domain)
 BOX = {"kR": (0.05, 0.6), "kh": (0.0, math.pi / 2), "ratio": (0.8, 1.5)}
+# where the network is trusted: the batch generator cannot make k R below
+# 2 pi R_min / edge_max = 2 pi 4 / 192, so smaller k R goes to the LB
+TRUST = {"kR": (2 * math.pi * 4.0 / 192.0, 0.6), "kh": BOX["kh"], "ratio": BOX["ratio"]}
 C0 = 1.0 / 3.0  # fluid sound speed of the batched boxes (keeps c_p <= 0.5 < 1/sqrt(3))
 
 _fp = C.POINTER(C.c_float)
@@ -75,9 +79,10 @@ def normalize(kR, kh, ratio) -> np.ndarray:
 
 
 def in_box(kR, kh, ratio) -> np.ndarray:
+    """True where the network is trusted (inside the training box)."""
     ok = np.ones(np.broadcast(np.asarray(kR), np.asarray(kh), np.asarray(ratio)).shape, bool)
     for v, key in ((kR, "kR"), (kh, "kh"), (ratio, "ratio")):
-        lo, hi = BOX[key]
+        lo, hi = TRUST[key]
         v = np.asarray(v)
         ok &= (v >= lo) & (v <= hi)
     return ok
