@@ -31,6 +31,10 @@ sys.path.insert(0, ROOT)
 METRIC = ("wave-LB MLUPS & % HBM roofline; forces/s plain vs batched/surrogate at "
           "≤2% error")
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0  # dense MFMA
+SURROGATE_DATA = os.path.join(ROOT, "paper_2404_02346_amd", "data")
+SURROGATE_TRAIN = ("lb_forces_seed2405_n4096.json",)
+SURROGATE_TEST = "lb_forces_seed2406_n512.json"
 SHAPE = (256, 128, 128)
 LAM, C0, CP_RATIO, RADIUS, NSURF = 256.0, 0.5, 1.1, 12.0, 2048
 N_POS = 16
@@ -43,6 +47,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true",
+                    help="skip training and timing the force surrogate")
+    ap.add_argument("--surrogate-batch", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--variant", default=None,
                     help="step-kernel variant 'cells_per_lane,x_mode,nontemporal' (skips autotune)")
@@ -80,7 +87,7 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage):
+def measured_traffic(storage, variant):
     """HBM bytes per step-kernel launch from the committed counter summary, if current."""
     path = os.path.join(ROOT, "profiles", "step_kernel_sphere16_traffic.json")
     try:
@@ -88,7 +95,8 @@ def measured_traffic(storage):
             d = json.load(fh)
     except OSError:
         return None
-    if d.get("kernel_source_sha") != kernel_source_sha() or d.get("storage") != storage:
+    if (d.get("kernel_source_sha") != kernel_source_sha() or d.get("storage") != storage
+            or tuple(d.get("variant", ())) != tuple(variant)):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -112,6 +120,52 @@ def cpu_baseline(x_mid, k, n_steps):
             "kind": "oracle",
             "sample": f"FP64 oracle, position kh_7 of 16, {n_steps} of 15360 steps on the full "
                       f"256x128x128 lattice with surface measurement ({dt:.1f} s)"}
+
+
+def surrogate_leg(stream, batch):
+    """Train the surrogate on the LB data, score it held out, time its fused inference."""
+    import torch
+    from paper_2404_02346_amd import surrogate as S
+    files = [os.path.join(SURROGATE_DATA, f) for f in SURROGATE_TRAIN]
+    test = os.path.join(SURROGATE_DATA, SURROGATE_TEST)
+    if not all(os.path.exists(f) for f in files + [test]):
+        return None
+    train_sets = [json.load(open(f)) for f in files]
+    net, log, train_s = S.fit(train_sets)
+    te = S.table(json.load(open(test)))
+    err = S.error_metric(net.predict(S.normalize(*te[:4])), te[4])
+    x = torch.rand(batch, S.N_IN, device="cuda") * 2 - 1
+    y = torch.empty(batch, device="cuda")
+    for _ in range(3):
+        net.forward_dev(x, y, batch)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n = 20
+    e0.record(stream)
+    for _ in range(n):
+        net.forward_dev(x, y, batch)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    net.close()
+    d = S.DIMS
+    flop = 2 * sum(d[i] * d[i + 1] for i in range(len(d) - 1))  # per sample
+    tflops = flop * batch / (ms * 1e-3) / 1e12
+    n_lb = sum(t["n"] for t in train_sets)
+    lb_s = sum(t["lb_seconds"] for t in train_sets)
+    return {
+        "forces_per_s": round(batch / (ms * 1e-3), 1),
+        "batched_lb_forces_per_s_same_boxes": round(n_lb / lb_s, 3),
+        "gain_over_batched_lb": round(batch / (ms * 1e-3) / (n_lb / lb_s), 1),
+        "held_out_error": {k: (round(v, 5) if isinstance(v, float) else v)
+                           for k, v in err.items()},
+        "test_samples": len(te[0]), "train_samples": n_lb,
+        "train_seconds": round(train_s, 2), "train_final_loss": log[-1][1],
+        "lb_seconds_for_training_data": round(lb_s, 1),
+        "inference": {"kernel": "infer_kernel (fused 4-256-256-256-256-1, BF16 MFMA)",
+                      "batch": batch, "ms": round(ms, 4), "flop_per_sample": flop,
+                      "tflops": round(tflops, 1),
+                      "frac_of_bf16_peak": round(tflops / BF16_PEAK_TFLOPS, 4)},
+    }
 
 
 def batch_workload(args):
@@ -234,11 +288,18 @@ def main():
     h.set_graph(args.graph)
     h.step(args.warmup)
     h.reset()  # the timed steps start the run from rest
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e0.record(stream)
     h.step(args.steps)
+    e1.record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # device time per step launch over the timed region (one fused launch per
+    # step; the interval also holds the graph-chunk counter updates and the two
+    # launches that drain the measurement pipeline at the end)
+    step_kernel_ms = e0.elapsed_time(e1) / args.steps
     ms_per_step = elapsed / args.steps * 1e3
     mlups = cells * args.steps / elapsed / 1e6
     F, nacc = h.force(allow_empty=True)
@@ -246,23 +307,22 @@ def main():
     h.close()
     del h
 
-    # --- dominant kernel alone (same instances and tile, no surface) timed with events ---
+    # --- the lattice stage alone (same instances and variant, no surface blocks) ---
     g = P.LBWave(problems(x_mid, k, with_surface=False), storage=args.storage, stream=stream)
     g.set_variant(*variant)
     g.set_graph(args.graph)
     g.step(10)
     n_k = min(max(args.steps // 10, 50), 1000)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     g.step(n_k)
     e1.record(stream)
     e1.synchronize()
-    kernel_ms = e0.elapsed_time(e1) / n_k
+    lattice_ms = e0.elapsed_time(e1) / n_k
     g.close()
     del g
     bytes_per_launch = 2 * Q * s * cells
-    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(args.storage)
+    achieved = bytes_per_launch / (step_kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(args.storage, variant)
 
     # --- copy reference: the same bytes through one read and one write stream ---
     half = bytes_per_launch // 2
@@ -321,8 +381,10 @@ def main():
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "kernel": "step_kernel<3,{},{},{},{}>".format(args.storage, *variant),
-            "kernel_ms": round(kernel_ms, 5),
+            "kernel_ms": round(step_kernel_ms, 5),
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            "lattice_stage_only_ms": round(lattice_ms, 5),
+            "lattice_stage_only_gbs": round(bytes_per_launch / (lattice_ms * 1e-3) / 1e9, 1),
             "copy_reference_gbs": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4),
         },
@@ -335,6 +397,11 @@ def main():
     if full_run:
         out["forces_x"] = [float(v) for v in F[:, 0]]
         out["n_accum"] = int(nacc[0])
+    if not args.no_surrogate:
+        sur = surrogate_leg(stream, args.surrogate_batch)
+        if sur is not None:
+            out["forces_per_s"]["surrogate"] = sur["forces_per_s"]
+            out["surrogate"] = sur
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(x_mid, k, args.cpu_steps)
     print(json.dumps(out), flush=True)

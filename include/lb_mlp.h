@@ -2,15 +2,18 @@
  * lb_mlp.h -- C ABI of the MLP surrogate of the time-averaged acoustic
  * radiation force (BF16 MFMA forward, backward and Adam on gfx950).
  *
- * The network maps three normalised inputs (k R, the position phase k h and
- * the contrast c_p/c0, each mapped to [-1, 1] by the caller) to the force
+ * The network maps four normalised inputs (k R, the position phase k h, the
+ * contrast c_p/c0 and the lattice resolution 1/R in inverse cells, each
+ * mapped to [-1, 1] by the caller) to the force
  * normalised by the small-sphere scale F0 = pi R^3 Pa^2 k / (3 rho0 c0^2) of
  * eq. ARF_Gorkov_3D (with it F/F0 tends to f1 sin 2kh as kR -> 0).  It is
  * trained on forces computed by the wave lattice Boltzmann library
  * (lb_wave.h), which stays the reference and the fallback outside the
- * training box.
+ * training box.  The resolution is an input because the lattice's answer at
+ * a given (k R, k h, c_p/c0) still depends on how many cells span the
+ * radius, by up to a few percent over R = 4 .. 16 cells.
  *
- * Architecture (fixed): 3 -> 256 -> 256 -> 256 -> 256 -> 1, exact-erf GELU
+ * Architecture (fixed): 4 -> 256 -> 256 -> 256 -> 256 -> 1, exact-erf GELU
  * after each hidden layer, linear output.  Parameters are FP32 masters, laid
  * out layer by layer as W_l (out x in, row-major) followed by b_l; the
  * matrix products run on MFMA with BF16 operands (weights, activations and
@@ -34,14 +37,17 @@ extern "C" {
 
 typedef struct lb_mlp lb_mlp;
 
-/* Number of FP32 parameters (198657). */
+/* Number of FP32 parameters (198913). */
 int32_t lb_mlp_num_params(void);
 
-/* Workspace bytes for batches of up to max_batch samples (0 if max_batch < 1). */
+/* Workspace bytes for training batches of up to max_batch samples (0 unless
+ * 1 <= max_batch <= 2^24). */
 size_t lb_mlp_workspace_bytes(int32_t max_batch);
 
 /* Create a handle on the caller's workspace and stream.  Parameters and the
- * Adam state start at zero; load parameters with lb_mlp_set_params. */
+ * Adam state start at zero; load parameters with lb_mlp_set_params.
+ * LB_EINVAL unless 1 <= max_batch <= 2^24; LB_ENOMEM if the workspace is
+ * smaller than lb_mlp_workspace_bytes(max_batch) or not 256-byte aligned. */
 int lb_mlp_create(int32_t max_batch, void *dev_workspace, size_t workspace_bytes,
                   void *hip_stream, lb_mlp **out);
 int lb_mlp_destroy(lb_mlp *h);  /* NULL-safe */
@@ -51,9 +57,19 @@ int lb_mlp_destroy(lb_mlp *h);  /* NULL-safe */
 int lb_mlp_set_params(lb_mlp *h, const float *host_params);
 int lb_mlp_get_params(lb_mlp *h, float *host_params);
 
-/* y = net(x) for B <= max_batch samples: dev_x B x 3 FP32, dev_y B FP32.
- * Asynchronous on the handle's stream. */
+/* y = net(x) for B >= 1 samples (any B: inference keeps no activations in
+ * the workspace): dev_x B x 4 FP32, dev_y B FP32.  One fused launch carries
+ * 128 samples per workgroup through every layer with the activations in LDS;
+ * operand roundings as in the training forward (BF16 weights and
+ * activations, FP32 accumulation and bias).  Asynchronous on the handle's
+ * stream. */
 int lb_mlp_forward(lb_mlp *h, const float *dev_x, int32_t B, float *dev_y);
+
+/* The training forward (one MFMA GEMM launch per layer, activations kept in
+ * the workspace for the backward pass) for B <= max_batch samples; same
+ * arguments as lb_mlp_forward.  Its output agrees with lb_mlp_forward up to
+ * the FP32 summation order.  Asynchronous. */
+int lb_mlp_forward_layered(lb_mlp *h, const float *dev_x, int32_t B, float *dev_y);
 
 /* Gradient of the mean squared error L = (1/B) sum (y - t)^2 with respect to
  * every parameter, without updating (host_grads: lb_mlp_num_params() floats;

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY (part of the oracle package; shares no code with
 the GPU library).  Plain numpy, float64 throughout.
 
-Network: 3 -> 256 -> 256 -> 256 -> 256 -> 1, exact GELU
+Network: 4 -> 256 -> 256 -> 256 -> 256 -> 1, exact GELU
 g(z) = z Phi(z) = z (1 + erf(z / sqrt 2)) / 2 after each hidden layer, linear
 output.  Parameters are one flat vector, layer by layer: W_l (out x in,
 row-major) then b_l.  Loss: mean squared error L = (1/B) sum (y - t)^2.
@@ -18,7 +18,7 @@ import math
 
 import numpy as np
 
-DIMS = (3, 256, 256, 256, 256, 1)
+DIMS = (4, 256, 256, 256, 256, 1)
 
 
 def num_params(dims=DIMS) -> int:

@@ -24,7 +24,8 @@ typedef short s16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLayers = 5;
-constexpr int kDims[kLayers + 1] = {3, 256, 256, 256, 256, 1};
+constexpr int kIn = 4;
+constexpr int kDims[kLayers + 1] = {kIn, 256, 256, 256, 256, 1};
 constexpr int kHidden = 256;
 
 constexpr int param_offset_w(int l)
@@ -173,13 +174,35 @@ __global__ void __launch_bounds__(256) loss_kernel(const float *y, const float *
     if (threadIdx.x == 0) *loss = red[0] / (double)B;
 }
 
-// db[n] = sum_b delta[b, n], one thread per column, batch order fixed
-__global__ void colsum_kernel(const float *delta, int B, int N, float *db)
+// db[n] = sum_b delta[b, n] in two deterministic passes.  Pass 1: block
+// (cg, s) sums rows 256 s .. 256 s + 255 of columns 64 cg .. 64 cg + 63;
+// thread (c, g) takes rows g, g + 4, ... of column c, then the four row
+// groups are added in order.  Pass 2: partials added in chunk order.
+constexpr int kColRows = 256;
+constexpr int kMaxTrainBatch = 1 << 24;  // keeps the column-sum grid within 65536 rows of blocks
+__global__ void __launch_bounds__(256) colsum_part_kernel(const float *delta, int B, int N,
+                                                          float *part)
+{
+    __shared__ float red[4][64];
+    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+    const int n = blockIdx.x * 64 + c;
+    const int b0 = blockIdx.y * kColRows;
+    const int b1 = min(b0 + kColRows, B);
+    float s = 0.f;
+    if (n < N)
+        for (int b = b0 + g; b < b1; b += 4) s += delta[(int64_t)b * N + n];
+    red[g][c] = s;
+    __syncthreads();
+    if (g == 0 && n < N)
+        part[(int64_t)blockIdx.y * N + n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+}
+
+__global__ void colsum_final_kernel(const float *part, int n_chunks, int N, float *db)
 {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
     float s = 0.f;
-    for (int b = 0; b < B; ++b) s += delta[(int64_t)b * N + n];
+    for (int k = 0; k < n_chunks; ++k) s += part[(int64_t)k * N + n];
     db[n] = s;
 }
 
@@ -229,16 +252,129 @@ __global__ void __launch_bounds__(64) mfma_probe_kernel(const uint16_t *A, const
     for (int v = 0; v < 4; ++v) D[(4 * (lane >> 4) + v) * 16 + (lane & 15)] = acc[v];
 }
 
+// Fused inference: one block carries kInferRows samples through all layers,
+// their activations staying in LDS (BF16, rows padded by 8 elements so that
+// the 16-byte fragment reads of 16 consecutive rows hit distinct banks).
+// Hidden layers run on MFMA with the same operand roundings as the training
+// forward: BF16 weights and activations, FP32 accumulation, FP32 bias, GELU
+// in FP32 rounded to BF16.  Each of the four wavefronts owns 64 output
+// columns for all kInferRows rows; its weight fragments come from global
+// memory (every block reads the same 128 KiB per layer, so they are L2 hits)
+// one K step ahead of use.
+constexpr int kInferRows = 128;
+constexpr int kActLd = kHidden + 8;
+
+__global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__ x, int B,
+                                                    const float *__restrict__ p,
+                                                    const uint16_t *__restrict__ pb,
+                                                    float *__restrict__ y)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t act[kInferRows][kActLd];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t row0 = (int64_t)blockIdx.x * kInferRows;
+
+    // layer 0 (K = kIn): FP32 sums of exact BF16 products, in k order, then the bias
+    {
+        const uint16_t *W = pb + param_offset_w(0);
+        const float *bias = p + param_offset_b(0);
+        const int n = tid;  // one output column per thread
+        float wn[kIn];
+#pragma unroll
+        for (int k = 0; k < kIn; ++k) wn[k] = bf2f(W[n * kIn + k]);
+        const float bn = bias[n];
+        for (int r = 0; r < kInferRows; ++r) {
+            const int64_t gr = row0 + r;
+            float z = 0.f;
+            if (gr < B) {
+#pragma unroll
+                for (int k = 0; k < kIn; ++k) z += bf2f(f2bf(x[gr * kIn + k])) * wn[k];
+            }
+            act[r][n] = f2bf(gelu(z + bn));
+        }
+    }
+    __syncthreads();
+
+    // hidden layers 1 .. kLayers-2 (256 x 256) on MFMA
+    for (int l = 1; l < kLayers - 1; ++l) {
+        const uint16_t *W = pb + param_offset_w(l);  // W[n][k], k fastest
+        const float *bias = p + param_offset_b(l);
+        f32x4 acc[kInferRows / 16][4];
+#pragma unroll
+        for (int i = 0; i < kInferRows / 16; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int kl = 8 * (lane >> 4);
+        s16x8 bnext[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = w * 64 + j * 16 + (lane & 15);
+            bnext[j] = *reinterpret_cast<const s16x8 *>(W + col * kHidden + kl);
+        }
+        for (int k0 = 0; k0 < kHidden; k0 += 32) {
+            bf16x8 bfr[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bfr[j] = __builtin_bit_cast(bf16x8, bnext[j]);
+            if (k0 + 32 < kHidden) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int col = w * 64 + j * 16 + (lane & 15);
+                    bnext[j] = *reinterpret_cast<const s16x8 *>(W + col * kHidden + k0 + 32 + kl);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kInferRows / 16; ++i) {
+                const bf16x8 af = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const s16x8 *>(&act[i * 16 + (lane & 15)][k0 + kl]));
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        __syncthreads();  // every wavefront has read this layer's input
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = w * 64 + j * 16 + (lane & 15);
+            const float bn = bias[col];
+#pragma unroll
+            for (int i = 0; i < kInferRows / 16; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    act[i * 16 + 4 * (lane >> 4) + v][col] = f2bf(gelu(acc[i][j][v] + bn));
+        }
+        __syncthreads();
+    }
+
+    // output layer (256 -> 1): two threads per row, FP32 sums of exact BF16 products
+    {
+        const uint16_t *W = pb + param_offset_w(kLayers - 1);
+        const float bias = p[param_offset_b(kLayers - 1)];
+        const int r = tid >> 1, half = tid & 1;
+        float s = 0.f;
+#pragma unroll 4
+        for (int c = 0; c < kHidden / 2; c += 8) {
+            const int k = half * (kHidden / 2) + c;
+            const s16x8 a = *reinterpret_cast<const s16x8 *>(&act[r][k]);
+            const s16x8 b = *reinterpret_cast<const s16x8 *>(W + k);
+#pragma unroll
+            for (int e = 0; e < 8; ++e) s += bf2f((uint16_t)a[e]) * bf2f((uint16_t)b[e]);
+        }
+        s += __shfl_xor(s, 1);
+        const int64_t gr = row0 + r;
+        if (half == 0 && gr < B) y[gr] = s + bias;
+    }
+}
+
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t p, g, m, v, pb;           // parameters, gradients, Adam moments, BF16 mirror
-    size_t xb;                       // BF16 input (B x 3)
+    size_t xb;                       // BF16 input (B x kIn)
     size_t act[kLayers];             // BF16 activations a_1..a_4 (B x 256); act[0] unused
     size_t z[kLayers];               // FP32 pre-activations z_0..z_3 (B x 256)
     size_t y;                        // FP32 output (B)
     size_t df[2], dbf[2];            // FP32 / BF16 errors, ping-pong (B x 256)
+    size_t part;                     // FP32 column-sum partials (ceil(B / 256) x 256)
     size_t loss;                     // FP64
     size_t total;
 };
@@ -257,7 +393,7 @@ Layout plan(int Bm)
     L.m = take(4 * (size_t)kParams);
     L.v = take(4 * (size_t)kParams);
     L.pb = take(2 * (size_t)kParams);
-    L.xb = take(2 * 3 * (size_t)Bm);
+    L.xb = take(2 * kIn * (size_t)Bm);
     for (int l = 0; l < kLayers; ++l) {
         L.act[l] = take(2 * (size_t)kHidden * Bm);
         L.z[l] = take(4 * (size_t)kHidden * Bm);
@@ -267,6 +403,7 @@ Layout plan(int Bm)
         L.df[i] = take(4 * (size_t)kHidden * Bm);
         L.dbf[i] = take(2 * (size_t)kHidden * Bm);
     }
+    L.part = take(4 * (size_t)kHidden * (((size_t)Bm + kColRows - 1) / kColRows));
     L.loss = take(8);
     L.total = off;
     return L;
@@ -304,9 +441,9 @@ GemmArgs base_args() { GemmArgs g; std::memset(&g, 0, sizeof g); return g; }
 // forward for B samples; keeps activations and pre-activations for backward
 void forward(const lb_mlp *h, const float *x, int B, float *y)
 {
-    const int64_t n3 = 3 * (int64_t)B;
-    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((n3 + 255) / 256)), dim3(256), 0, h->stream,
-                       x, h->at<uint16_t>(h->L.xb), n3);
+    const int64_t nx = kIn * (int64_t)B;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream,
+                       x, h->at<uint16_t>(h->L.xb), nx);
     const uint16_t *a = h->at<uint16_t>(h->L.xb);
     for (int l = 0; l < kLayers; ++l) {
         const int K = kDims[l], N = kDims[l + 1];
@@ -362,8 +499,12 @@ void backward(const lb_mlp *h, const float *t, int B)
         g.outf = h->at<float>(h->L.g) + param_offset_w(l);
         g.ldo = K;
         gemm(h, g);
-        hipLaunchKernelGGL(colsum_kernel, dim3((N + 255) / 256), dim3(256), 0, h->stream,
-                           h->at<float>(h->L.df[cur]), B, N, h->at<float>(h->L.g) + param_offset_b(l));
+        const int n_chunks = (B + kColRows - 1) / kColRows;
+        hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, n_chunks), dim3(256), 0,
+                           h->stream, h->at<float>(h->L.df[cur]), B, N, h->at<float>(h->L.part));
+        hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 255) / 256), dim3(256), 0, h->stream,
+                           h->at<float>(h->L.part), n_chunks, N,
+                           h->at<float>(h->L.g) + param_offset_b(l));
         if (l == 0) break;
         // delta_{l-1} (B x K) = (delta_l (B x N) W_l (N x K)) * gelu'(z_{l-1})
         GemmArgs d = base_args();
@@ -401,7 +542,7 @@ int32_t lb_mlp_num_params(void) { return kParams; }
 
 size_t lb_mlp_workspace_bytes(int32_t max_batch)
 {
-    if (max_batch < 1) return 0;
+    if (max_batch < 1 || max_batch > kMaxTrainBatch) return 0;
     return plan(max_batch).total;
 }
 
@@ -410,7 +551,8 @@ int lb_mlp_create(int32_t max_batch, void *dev_workspace, size_t workspace_bytes
 {
     if (!out) return lbw_fail_msg(LB_EINVAL, "out is NULL");
     *out = nullptr;
-    if (max_batch < 1) return lbw_fail_msg(LB_EINVAL, "max_batch must be >= 1");
+    if (max_batch < 1 || max_batch > kMaxTrainBatch)
+        return lbw_fail_msg(LB_EINVAL, "max_batch must be in 1 .. 2^24");
     Layout L = plan(max_batch);
     if (!dev_workspace || reinterpret_cast<uintptr_t>(dev_workspace) % kAlign)
         return lbw_fail_msg(LB_ENOMEM, "workspace must be 256-byte aligned device memory");
@@ -466,6 +608,18 @@ int lb_mlp_get_params(lb_mlp *h, float *host_params)
 }
 
 int lb_mlp_forward(lb_mlp *h, const float *dev_x, int32_t B, float *dev_y)
+{
+    if (!h) return lbw_fail_msg(LB_EINVAL, "handle is NULL");
+    if (B < 1) return lbw_fail_msg(LB_EINVAL, "batch must be >= 1");
+    if (!dev_x || !dev_y) return lbw_fail_msg(LB_EINVAL, "NULL argument");
+    const unsigned blocks = (unsigned)(((int64_t)B + kInferRows - 1) / kInferRows);
+    hipLaunchKernelGGL(infer_kernel, dim3(blocks), dim3(256), 0, h->stream, dev_x, B,
+                       h->at<float>(h->L.p), h->at<uint16_t>(h->L.pb), dev_y);
+    MLP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+int lb_mlp_forward_layered(lb_mlp *h, const float *dev_x, int32_t B, float *dev_y)
 {
     int st = check_batch(h, B);
     if (st) return st;

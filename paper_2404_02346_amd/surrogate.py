@@ -1,10 +1,13 @@
 """MLP surrogate of the time-averaged radiation force, trained on batched LB runs.
 
 The network (include/lb_mlp.h; BF16 MFMA forward, backward and Adam kernels in
-csrc/lb_mlp.hip) maps (k R, k h, c_p/c0), each mapped linearly from the
+csrc/lb_mlp.hip) maps (k R, k h, c_p/c0, 1/R), each mapped linearly from the
 training box to [-1, 1], to F / F0 with F0 = pi R^3 Pa^2 k / (3 rho0 c0^2),
 the scale of the small-sphere force (eq. ARF_Gorkov_3D): F/F0 -> f1 sin 2kh
-as kR -> 0, f1 = 1 - c0^2/c_p^2 for a density-matched sphere.
+as kR -> 0, f1 = 1 - c0^2/c_p^2 for a density-matched sphere.  R is the
+radius in lattice cells: at fixed (k R, k h, c_p/c0) the lattice's force
+still moves by a few percent between R = 4 and R = 16 cells, so the
+resolution is an input (left out, it is scatter the network cannot fit).
 
 Training data come from the batched lattice Boltzmann runs (lbwave.LBWave
 with many uneven instances); the same LB stays the reference for the error
@@ -19,11 +22,15 @@ import numpy as np
 
 from . import lbwave
 
-# input box mapped to [-1, 1] (the network's nominal domain)
-BOX = {"kR": (0.05, 0.6), "kh": (0.0, math.pi / 2), "ratio": (0.8, 1.5)}
+# input box mapped to [-1, 1] (the network's nominal domain); the fourth
+# input is 1/R with R the radius in cells, R in 4 .. 16
+BOX = {"kR": (0.05, 0.6), "kh": (0.0, math.pi / 2), "ratio": (0.8, 1.5),
+       "inv_R": (1.0 / 16.0, 1.0 / 4.0)}
 # where the network is trusted: the batch generator cannot make k R below
 # 2 pi R_min / edge_max = 2 pi 4 / 192, so smaller k R goes to the LB
-TRUST = {"kR": (2 * math.pi * 4.0 / 192.0, 0.6), "kh": BOX["kh"], "ratio": BOX["ratio"]}
+TRUST = {"kR": (2 * math.pi * 4.0 / 192.0, 0.6), "kh": BOX["kh"], "ratio": BOX["ratio"],
+         "inv_R": BOX["inv_R"]}
+N_IN = 4
 C0 = 1.0 / 3.0  # fluid sound speed of the batched boxes (keeps c_p <= 0.5 < 1/sqrt(3))
 
 _fp = C.POINTER(C.c_float)
@@ -41,6 +48,7 @@ def _mlp_lib():
         L.lb_mlp_set_params.argtypes = [vp, _fp]
         L.lb_mlp_get_params.argtypes = [vp, _fp]
         L.lb_mlp_forward.argtypes = [vp, vp, C.c_int32, vp]
+        L.lb_mlp_forward_layered.argtypes = [vp, vp, C.c_int32, vp]
         L.lb_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, _fp, C.POINTER(C.c_double)]
         L.lb_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float,
                                         C.c_float]
@@ -54,7 +62,7 @@ def num_params() -> int:
     return int(_mlp_lib().lb_mlp_num_params())
 
 
-DIMS = (3, 256, 256, 256, 256, 1)
+DIMS = (N_IN, 256, 256, 256, 256, 1)
 
 
 def init_params(seed: int) -> np.ndarray:
@@ -69,22 +77,28 @@ def init_params(seed: int) -> np.ndarray:
     return np.concatenate(out).astype(np.float32)
 
 
-def normalize(kR, kh, ratio) -> np.ndarray:
-    """Map (kR, kh, c_p/c0) from the training box to [-1, 1]^3 (B x 3 float32)."""
+def _inputs(kR, kh, ratio, R):
+    kR, kh, ratio, R = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64)
+                                             for v in (kR, kh, ratio, R)))
+    return ((kR, "kR"), (kh, "kh"), (ratio, "ratio"), (1.0 / R, "inv_R"))
+
+
+def normalize(kR, kh, ratio, R) -> np.ndarray:
+    """Map (kR, kh, c_p/c0, 1/R) from the training box to [-1, 1]^4 (B x 4 float32)."""
     cols = []
-    for v, key in ((kR, "kR"), (kh, "kh"), (ratio, "ratio")):
+    for v, key in _inputs(kR, kh, ratio, R):
         lo, hi = BOX[key]
-        cols.append(2.0 * (np.asarray(v, dtype=np.float64) - lo) / (hi - lo) - 1.0)
-    return np.stack(cols, axis=-1).astype(np.float32).reshape(-1, 3)
+        cols.append(2.0 * (v - lo) / (hi - lo) - 1.0)
+    return np.stack(cols, axis=-1).astype(np.float32).reshape(-1, N_IN)
 
 
-def in_box(kR, kh, ratio) -> np.ndarray:
+def in_box(kR, kh, ratio, R) -> np.ndarray:
     """True where the network is trusted (inside the training box)."""
-    ok = np.ones(np.broadcast(np.asarray(kR), np.asarray(kh), np.asarray(ratio)).shape, bool)
-    for v, key in ((kR, "kR"), (kh, "kh"), (ratio, "ratio")):
+    cols = _inputs(kR, kh, ratio, R)
+    ok = np.ones(cols[0][0].shape, bool)
+    for v, key in cols:
         lo, hi = TRUST[key]
-        v = np.asarray(v)
-        ok &= (v >= lo) & (v <= hi)
+        ok &= (v >= lo * (1 - 1e-12)) & (v <= hi * (1 + 1e-12))
     return ok
 
 
@@ -129,23 +143,26 @@ class MLP:
         t = torch.as_tensor(np.ascontiguousarray(np.asarray(a, dtype=np.float32)), device="cuda")
         return t if cols is None else t.reshape(-1, cols)
 
-    def forward_dev(self, x_dev, y_dev, B: int):
-        lbwave._check(_mlp_lib().lb_mlp_forward(self._h, C.c_void_p(x_dev.data_ptr()), int(B),
-                                                C.c_void_p(y_dev.data_ptr())))
+    def forward_dev(self, x_dev, y_dev, B: int, layered: bool = False):
+        """y = net(x) on device tensors: the fused inference launch, or the training forward."""
+        fn = _mlp_lib().lb_mlp_forward_layered if layered else _mlp_lib().lb_mlp_forward
+        lbwave._check(fn(self._h, C.c_void_p(x_dev.data_ptr()), int(B),
+                         C.c_void_p(y_dev.data_ptr())))
 
-    def predict(self, x) -> np.ndarray:
+    def predict(self, x, layered: bool = False, chunk: int = 1 << 22) -> np.ndarray:
         import torch
-        x = np.asarray(x, dtype=np.float32).reshape(-1, 3)
+        x = np.asarray(x, dtype=np.float32).reshape(-1, N_IN)
         out = np.empty(len(x), dtype=np.float32)
-        for s in range(0, len(x), self.max_batch):
-            xb = self._dev(x[s: s + self.max_batch], 3)
+        step = self.max_batch if layered else chunk
+        for s in range(0, len(x), step):
+            xb = self._dev(x[s: s + step], N_IN)
             yb = torch.empty(len(xb), dtype=torch.float32, device="cuda")
-            self.forward_dev(xb, yb, len(xb))
+            self.forward_dev(xb, yb, len(xb), layered)
             out[s: s + len(xb)] = yb.cpu().numpy()
         return out
 
     def grad(self, x, t):
-        x_d, t_d = self._dev(x, 3), self._dev(t)
+        x_d, t_d = self._dev(x, N_IN), self._dev(t)
         g = np.empty(num_params(), dtype=np.float32)
         loss = C.c_double()
         lbwave._check(_mlp_lib().lb_mlp_grad(self._h, C.c_void_p(x_d.data_ptr()),
@@ -158,11 +175,11 @@ class MLP:
               log_every: int = 0):
         """Adam on the mean squared error; mini-batches drawn with a seeded permutation."""
         import torch
-        x = np.asarray(x, dtype=np.float32).reshape(-1, 3)
+        x = np.asarray(x, dtype=np.float32).reshape(-1, N_IN)
         t = np.asarray(t, dtype=np.float32).reshape(-1)
         n = len(t)
         batch = min(batch or n, self.max_batch, n)
-        x_d, t_d = self._dev(x, 3), self._dev(t)
+        x_d, t_d = self._dev(x, N_IN), self._dev(t)
         rng = np.random.Generator(np.random.PCG64(seed))
         L = _mlp_lib()
         losses = []
@@ -246,8 +263,13 @@ def run_batch(problems, storage: str = "f32", autotune: bool = True, stream=None
 
 
 def generate(seed: int, n: int, cal=None, kr_max: float = 0.6, storage: str = "f32",
-             chunk: int = 256, n_periods: int = 30, avg_periods: int = 10):
-    """Seeded samples of the batch generator (k R <= kr_max) with their LB forces."""
+             chunk: int = 256, n_periods: int = 30, avg_periods: int = 10, start: int = 0):
+    """Seeded samples start .. n-1 of the batch generator (k R <= kr_max) with their LB forces.
+
+    The draws are sequential, so samples [a, b) and [b, c) together are
+    samples [a, c); every instance runs independently of the others in its
+    handle, so the forces do not depend on how the samples are split.
+    """
     import workloads
     cal = cal or calibrate_edges(workloads.BATCH_EDGES)
     x_mid = {e: c["x_mid"] for e, c in cal.items()}
@@ -255,8 +277,8 @@ def generate(seed: int, n: int, cal=None, kr_max: float = 0.6, storage: str = "f
     probs, info = workloads.batch(seed, n, x_mid, kk, kr_max=kr_max, n_periods=n_periods,
                                   avg_periods=avg_periods, return_draws=True)
     rows, secs, upd = [], 0.0, 0
-    for s in range(0, n, chunk):
-        part = probs[s: s + chunk]
+    for s in range(start, n, chunk):
+        part = probs[s: min(s + chunk, n)]
         r = run_batch(part, storage=storage)
         secs += r["seconds"]
         upd += r["updates"]
@@ -269,16 +291,54 @@ def generate(seed: int, n: int, cal=None, kr_max: float = 0.6, storage: str = "f
             rows.append({"edge": int(p["nx"]), "R": R, "ratio": p["cp_ratio"], "kh": p["kh"],
                          "kR": 2 * math.pi * R / lam, "F": [float(v) for v in F],
                          "F_over_F0": float(F[0] / F0)})
-    return {"seed": seed, "n": n, "kr_max": kr_max, "storage": storage, "rows": rows,
-            "rejected_draws": info["rejected"], "lb_seconds": secs, "lb_updates": upd}
+    return {"seed": seed, "n": n - start, "start": start, "kr_max": kr_max, "storage": storage,
+            "rows": rows, "rejected_draws": info["rejected"], "lb_seconds": secs,
+            "lb_updates": upd}
 
 
-def table(data):
-    kR = np.array([r["kR"] for r in data["rows"]])
-    kh = np.array([r["kh"] for r in data["rows"]])
-    ratio = np.array([r["ratio"] for r in data["rows"]])
-    y = np.array([r["F_over_F0"] for r in data["rows"]])
-    return kR, kh, ratio, y
+def merge(parts):
+    """Join consecutive sample ranges of one seed (as written by generate) into one data set."""
+    parts = sorted(parts, key=lambda d: d.get("start", 0))
+    pos = parts[0].get("start", 0)
+    for d in parts:
+        if d["seed"] != parts[0]["seed"] or d["kr_max"] != parts[0]["kr_max"] \
+                or d["storage"] != parts[0]["storage"] or d.get("start", 0) != pos:
+            raise ValueError("parts are not consecutive ranges of one seeded data set")
+        pos += d["n"]
+    rows = [r for d in parts for r in d["rows"]]
+    return {"seed": parts[0]["seed"], "n": len(rows), "start": parts[0].get("start", 0),
+            "kr_max": parts[0]["kr_max"], "storage": parts[0]["storage"], "rows": rows,
+            "rejected_draws": parts[-1]["rejected_draws"],
+            "lb_seconds": sum(d["lb_seconds"] for d in parts),
+            "lb_updates": sum(d["lb_updates"] for d in parts)}
+
+
+def table(*datasets):
+    """Columns (kR, kh, c_p/c0, R in cells, F/F0) over the rows of one or more data sets."""
+    rows = [r for d in datasets for r in d["rows"]]
+    return tuple(np.array([r[key] for r in rows]) for key in ("kR", "kh", "ratio", "R",
+                                                                "F_over_F0"))
+
+
+def fit(train_sets, steps: int = 8000, lr: float = 2e-3, lr_final: float = 3e-5, seed: int = 0,
+        batch: int | None = None, log_every: int = 2000):
+    """Train a network on LB data sets with the standard recipe.
+
+    Adam on the mean squared error of F/F0, learning rate decayed
+    geometrically from lr to lr_final, full batch unless ``batch`` is given.
+    Returns (network, loss log, seconds).
+    """
+    import time
+
+    import torch
+    tr = table(*train_sets)
+    net = MLP(max_batch=len(tr[0]), seed=seed)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    log = net.train(normalize(*tr[:4]), tr[4], steps=steps, lr=lr, lr_final=lr_final,
+                    batch=batch, log_every=log_every)
+    torch.cuda.synchronize()
+    return net, log, time.perf_counter() - t0
 
 
 def closed_form_ratio(kh, ratio):
@@ -287,43 +347,56 @@ def closed_form_ratio(kh, ratio):
 
 
 def error_metric(pred, ref):
-    """max |pred - ref| / max |ref| over the set, and its RMS counterpart."""
-    pred, ref = np.asarray(pred), np.asarray(ref)
+    """max |pred - ref| / max |ref| over the set and its RMS counterpart, plus the
+    plain relative error max |pred - ref| / |ref| over the samples with
+    |ref| >= 0.2 max |ref| (away from the zeros of the force)."""
+    pred, ref = np.asarray(pred, dtype=np.float64), np.asarray(ref, dtype=np.float64)
     scale = np.abs(ref).max()
     e = np.abs(pred - ref) / scale
-    return {"max": float(e.max()), "rms": float(np.sqrt(np.mean(e ** 2)))}
+    big = np.abs(ref) >= 0.2 * scale
+    rel = np.abs(pred - ref)[big] / np.abs(ref[big])
+    return {"max": float(e.max()), "rms": float(np.sqrt(np.mean(e ** 2))),
+            "rel_max_large": float(rel.max()), "n_large": int(big.sum())}
 
 
 class Surrogate:
-    """Trained network with the plain LB as fallback outside the training box."""
+    """Trained network with the plain LB as fallback outside the training box.
 
-    def __init__(self, mlp: MLP, lb_edge: int = 128, cal=None):
+    A fallback query runs a cubic box of edge = wavelength = 2 pi R / kR
+    cells (rounded, at least min_edge), so that it keeps the requested
+    resolution R as closely as the integer edge allows.
+    """
+
+    def __init__(self, mlp: MLP, min_edge: int = 32, cal=None):
         self.mlp = mlp
-        self.lb_edge = lb_edge
-        self.cal = cal
+        self.min_edge = min_edge
+        self.cal = dict(cal or {})
 
-    def predict(self, kR, kh, ratio):
-        """F/F0 for each query; LB runs for the queries outside the box."""
+    def predict(self, kR, kh, ratio, R):
+        """F/F0 for each query (R in cells); LB runs for the queries outside the box."""
         import workloads
-        kR, kh, ratio = (np.atleast_1d(np.asarray(v, dtype=np.float64)) for v in (kR, kh, ratio))
-        ok = in_box(kR, kh, ratio)
+        kR, kh, ratio, R = (np.atleast_1d(v) for v in
+                            np.broadcast_arrays(*(np.asarray(v, dtype=np.float64)
+                                                  for v in (kR, kh, ratio, R))))
+        ok = in_box(kR, kh, ratio, R)
         out = np.empty(kR.shape)
         if ok.any():
-            out[ok] = self.mlp.predict(normalize(kR[ok], kh[ok], ratio[ok]))
+            out[ok] = self.mlp.predict(normalize(kR[ok], kh[ok], ratio[ok], R[ok]))
         bad = np.where(~ok)[0]
         if len(bad):
-            e = self.lb_edge
-            if self.cal is None or e not in self.cal:
-                self.cal = calibrate_edges([e])
-            c = self.cal[e]
+            edges = [max(self.min_edge, int(round(2 * math.pi * R[i] / kR[i]))) for i in bad]
+            missing = sorted(set(edges) - set(self.cal))
+            if missing:
+                self.cal.update(calibrate_edges(missing))
             probs = []
-            for i in bad:
-                R = kR[i] * e / (2 * math.pi)
+            for i, e in zip(bad, edges):
+                c = self.cal[e]
                 p = workloads.sphere_3d(c["x_mid"], c["k"], float(kh[i]), shape=(e, e, e),
-                                        lam=float(e), R=float(R), cp_ratio=float(ratio[i]),
-                                        n_surf=2048, c0=C0)
+                                        lam=float(e), R=float(kR[i] * e / (2 * math.pi)),
+                                        cp_ratio=float(ratio[i]), n_surf=2048, c0=C0)
                 probs.append(p)
             r = run_batch(probs, autotune=False)
-            for j, i in enumerate(bad):
-                out[i] = r["F"][j, 0] / force_scale(probs[j]["radius"], c["Pa"], float(e))
+            for j, (i, e) in enumerate(zip(bad, edges)):
+                out[i] = r["F"][j, 0] / force_scale(probs[j]["radius"], self.cal[e]["Pa"],
+                                                     float(e))
         return out, ~ok

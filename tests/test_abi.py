@@ -10,7 +10,7 @@ import pytest
 import workloads
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "lb_wave.h")
+HEADERS = [os.path.join(ROOT, "include", f) for f in ("lb_wave.h", "lb_mlp.h")]
 
 
 @pytest.fixture(scope="module")
@@ -24,15 +24,18 @@ def P():
 
 
 def declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(lb_\w+)\s*\(", src)) - {"lb_wave_desc"})
+    names = set()
+    for h in HEADERS:
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(lb_\w+)\s*\(", src))
+    return sorted(names - {"lb_wave_desc"})
 
 
 def test_header_declares_the_core_calls():
     names = declared_functions()
     for core in ("lb_wave_create", "lb_wave_step_n", "lb_surface_force", "lb_wave_destroy",
-                 "lb_wave_workspace_bytes", "lb_wave_check", "lb_cavity_calibrate"):
+                 "lb_wave_workspace_bytes", "lb_wave_check", "lb_cavity_calibrate",
+                 "lb_mlp_create", "lb_mlp_forward", "lb_mlp_train_step", "lb_mlp_destroy"):
         assert core in names
 
 
@@ -163,3 +166,22 @@ def test_create_rejects_bad_workspace_without_device_work(P):
     assert lib.lb_wave_create(arr, 1, ctypes.c_void_p(257), 1 << 40, None, ctypes.byref(h)) == -2
     assert lib.lb_wave_destroy(None) == 0
     assert lib.lb_wave_step_n(None, 1) == -1
+
+
+def test_mlp_sizes_and_argument_errors(P):
+    # the surrogate network's host-side checks: sizes and errors before any device call
+    from oracle import mlp_oracle as M
+    lib = P.lib()
+    lib.lb_mlp_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.lb_mlp_num_params() == M.num_params()
+    assert lib.lb_mlp_workspace_bytes(0) == 0
+    assert lib.lb_mlp_workspace_bytes((1 << 24) + 1) == 0
+    small, big = lib.lb_mlp_workspace_bytes(256), lib.lb_mlp_workspace_bytes(4096)
+    assert 0 < small < big and small % 256 == 0
+    h = ctypes.c_void_p()
+    assert lib.lb_mlp_create(0, ctypes.c_void_p(256), 1 << 40, None, ctypes.byref(h)) == -1
+    assert lib.lb_mlp_create(256, None, 1 << 40, None, ctypes.byref(h)) == -2
+    assert lib.lb_mlp_create(256, ctypes.c_void_p(256), 10, None, ctypes.byref(h)) == -2
+    assert lib.lb_mlp_forward(None, None, 1, None) == -1
+    assert lib.lb_mlp_forward_layered(None, None, 1, None) == -1
+    assert lib.lb_mlp_destroy(None) == 0

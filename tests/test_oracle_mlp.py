@@ -15,7 +15,7 @@ def _params(seed, dims):
 
 
 def test_num_params():
-    assert M.num_params() == 198657
+    assert M.num_params() == 198913
 
 
 def test_gelu_values():
@@ -52,7 +52,7 @@ def test_gradient_against_autograd():
     torch = pytest.importorskip("torch")
     p = _params(3, M.DIMS) * 0.1
     rng = np.random.Generator(np.random.PCG64(4))
-    x = rng.uniform(-1, 1, size=(33, 3))
+    x = rng.uniform(-1, 1, size=(33, M.DIMS[0]))
     t = rng.normal(size=33)
     loss, g = M.loss_and_grad(p, x, t)
     pt = torch.tensor(p, dtype=torch.float64, requires_grad=True)
