@@ -52,7 +52,8 @@ def parse():
     ap.add_argument("--surrogate-batch", type=int, default=1 << 20)
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--variant", default=None,
-                    help="step-kernel variant 'cells_per_lane,x_mode,nontemporal' (skips autotune)")
+                    help="kernel variant 'cells_per_lane,x_mode,nontemporal[,steps_per_launch]' "
+                         "(skips autotune)")
     ap.add_argument("--workload", default="sphere", choices=["sphere", "batch"],
                     help="sphere: the 16-position 3D sphere (default); batch: the seeded uneven "
                          "batch of boxes (forces/s batched vs plain)")
@@ -87,9 +88,26 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
+def set_variant(h, v):
+    """Apply (cells_per_lane, x_mode, nontemporal, steps_per_launch) to a handle."""
+    h.set_steps_per_launch(v[3])
+    h.set_variant(*v[:3])
+
+
+def get_variant(h):
+    return tuple(h.variant()) + (h.steps_per_launch(),)
+
+
+def kernel_name(storage, v):
+    if v[3] == 2:
+        return "step2_kernel<{},rows={},nt={}>".format(storage, 2 if storage == "f64" else 4,
+                                                       min(v[2], 1))
+    return "step_kernel<3,{},{},{},{}>".format(storage, *v[:3])
+
+
 def measured_traffic(storage, variant):
     """HBM bytes per step-kernel launch from the committed counter summary, if current."""
-    path = os.path.join(ROOT, "profiles", "step_kernel_sphere16_traffic.json")
+    path = os.path.join(ROOT, "profiles", "step2_kernel_sphere16_traffic.json")
     try:
         with open(path) as fh:
             d = json.load(fh)
@@ -243,13 +261,16 @@ def main():
     probs = problems(x_mid, k)
     cells = N_POS * SHAPE[0] * SHAPE[1] * SHAPE[2]
     Q, s = 7, {"f32": 4, "f16": 2, "bf16": 2}[args.storage]
-    fixed = tuple(int(v) for v in args.variant.split(",")) if args.variant else None
+    fixed = None
+    if args.variant:
+        fixed = tuple(int(v) for v in args.variant.split(","))
+        fixed = fixed + (1,) * (4 - len(fixed))
 
     if args.kernel_only:
         # step kernel alone, then the copy of the same byte count, K launches each
         g = P.LBWave(problems(x_mid, k, with_surface=False), storage=args.storage, stream=stream)
         if fixed:
-            g.set_variant(*fixed)
+            set_variant(g, fixed)
         g.set_graph(args.graph)
         g.step(args.warmup)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -258,7 +279,7 @@ def main():
         e1.record(stream)
         e1.synchronize()
         kms = e0.elapsed_time(e1) / args.steps
-        variant = g.variant()
+        variant = get_variant(g)
         g.close()
         del g
         half = 2 * Q * s * cells // 2
@@ -271,20 +292,20 @@ def main():
         e1.synchronize()
         cms = e0.elapsed_time(e1) / args.steps
         print(json.dumps({"mode": "kernel-only", "variant": variant, "storage": args.storage,
-                          "launches": args.steps, "step_kernel_ms": kms,
-                          "step_kernel_gbs": 2 * half / kms / 1e6, "copy_bytes": 2 * half,
+                          "steps": args.steps, "ms_per_step": kms,
+                          "one_step_equivalent_gbs": 2 * half / kms / 1e6, "copy_bytes": 2 * half,
                           "copy_ms": cms, "copy_gbs": 2 * half / cms / 1e6}), flush=True)
         return
 
     # --- whole hot path: step kernel + surface measurement, 16 instances ---
     h = P.LBWave(probs, storage=args.storage, stream=stream)
     if fixed:
-        h.set_variant(*fixed)
+        set_variant(h, fixed)
         tune_ms = None
     else:
         tune_ms = h.autotune(6)
-    variant = h.variant()
-    tile = variant[0]
+    variant = get_variant(h)
+    spl = variant[3]
     h.set_graph(args.graph)
     h.step(args.warmup)
     h.reset()  # the timed steps start the run from rest
@@ -296,10 +317,11 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    # device time per step launch over the timed region (one fused launch per
-    # step; the interval also holds the graph-chunk counter updates and the two
-    # launches that drain the measurement pipeline at the end)
-    step_kernel_ms = e0.elapsed_time(e1) / args.steps
+    # device time per launch over the timed region (one launch per spl steps,
+    # the surface measurement fused in; the interval also holds the
+    # graph-chunk counter updates and the launches that drain the measurement
+    # pipeline at the end)
+    launch_ms = e0.elapsed_time(e1) / args.steps * spl
     ms_per_step = elapsed / args.steps * 1e3
     mlups = cells * args.steps / elapsed / 1e6
     F, nacc = h.force(allow_empty=True)
@@ -309,7 +331,7 @@ def main():
 
     # --- the lattice stage alone (same instances and variant, no surface blocks) ---
     g = P.LBWave(problems(x_mid, k, with_surface=False), storage=args.storage, stream=stream)
-    g.set_variant(*variant)
+    set_variant(g, variant)
     g.set_graph(args.graph)
     g.step(10)
     n_k = min(max(args.steps // 10, 50), 1000)
@@ -317,11 +339,13 @@ def main():
     g.step(n_k)
     e1.record(stream)
     e1.synchronize()
-    lattice_ms = e0.elapsed_time(e1) / n_k
+    lattice_ms = e0.elapsed_time(e1) / n_k * spl  # per launch
     g.close()
     del g
+    # algorithmic HBM bytes of one launch: the state read once and written
+    # once (2 Q s per cell), whether the launch advances one step or two
     bytes_per_launch = 2 * Q * s * cells
-    achieved = bytes_per_launch / (step_kernel_ms * 1e-3) / 1e9
+    achieved = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(args.storage, variant)
 
     # --- copy reference: the same bytes through one read and one write stream ---
@@ -341,7 +365,7 @@ def main():
 
     # --- plain single-instance rate for the forces/s comparison ---
     one = P.LBWave([probs[7]], storage=args.storage, stream=stream)
-    one.set_variant(*variant)
+    set_variant(one, variant)
     one.set_graph(args.graph)
     one.step(10)
     torch.cuda.synchronize()
@@ -372,7 +396,7 @@ def main():
                         "in one handle, 30 periods (15360 steps), average over the last 10",
             "instances": N_POS, "cells_per_step": cells, "storage": args.storage,
             "kernel_variant": {"cells_per_lane": variant[0], "x_mode": variant[1],
-                               "nontemporal": variant[2]},
+                               "nontemporal": variant[2], "steps_per_launch": spl},
             "graph_chunk": args.graph,
             "x_antinode": round(x_mid, 4), "Pa": cal["Pa"],
         },
@@ -380,9 +404,11 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "step_kernel<3,{},{},{},{}>".format(args.storage, *variant),
-            "kernel_ms": round(step_kernel_ms, 5),
+            "kernel": kernel_name(args.storage, variant),
+            "kernel_ms": round(launch_ms, 5),
+            "steps_per_launch": spl,
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            "one_step_equivalent_gbs": round(achieved * spl, 1),
             "lattice_stage_only_ms": round(lattice_ms, 5),
             "lattice_stage_only_gbs": round(bytes_per_launch / (lattice_ms * 1e-3) / 1e9, 1),
             "copy_reference_gbs": round(copy_gbs, 1),

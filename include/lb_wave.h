@@ -174,9 +174,10 @@ int lb_wave_state_view(const lb_wave *h, int32_t inst, lb_state_view *v);
  *   nontemporal 0: plain loads and stores, 1: non-temporal stores,
  *     2: non-temporal loads and stores.
  * Every variant computes bit-identical results.  lb_wave_autotune times every
- * valid variant for n_trial steps on the handle's own instances, keeps the
- * fastest, then resets the state (lb_wave_reset); best_ms (may be NULL)
- * receives the winning time per step in ms.  set_tile/get_tile change or read
+ * valid variant, and two steps per launch where allowed, for n_trial steps
+ * (rounded up to even) on the handle's own instances, keeps the fastest,
+ * then resets the state (lb_wave_reset); best_ms (may be NULL) receives the
+ * winning time per step in ms.  set_tile/get_tile change or read
  * cells_per_lane only. */
 int lb_wave_set_variant(lb_wave *h, int32_t cells_per_lane, int32_t x_mode, int32_t nontemporal);
 int lb_wave_get_variant(const lb_wave *h, int32_t *cells_per_lane, int32_t *x_mode,
@@ -184,6 +185,17 @@ int lb_wave_get_variant(const lb_wave *h, int32_t *cells_per_lane, int32_t *x_mo
 int lb_wave_set_tile(lb_wave *h, int32_t cells_per_lane);
 int lb_wave_get_tile(const lb_wave *h, int32_t *cells_per_lane);
 int lb_wave_autotune(lb_wave *h, int32_t n_trial, double *best_ms);
+
+/* Lattice steps per launch: 1 (step_kernel, the default) or 2 (a fused
+ * kernel that advances t -> t + 2 with step t's values held on chip, reading
+ * and writing the state about once per two steps).  Two steps per launch
+ * need every instance 3D with driven x sheets, nx <= 256 and ny a multiple
+ * of the row block (4 rows for 4- and 2-byte storage, 2 for FP64, times
+ * 256 / pitch row groups); otherwise LB_EINVAL.  Results are bit-identical
+ * either way; steps where an instance stops, and odd remainders, run one at
+ * a time.  lb_wave_autotune also tries two steps per launch when allowed. */
+int lb_wave_set_steps_per_launch(lb_wave *h, int32_t k);
+int lb_wave_get_steps_per_launch(const lb_wave *h, int32_t *k);
 
 /* Replay steady steps as captured HIP graphs of `chunk` steps (0 = off,
  * otherwise 2..4096).  A sequence is captured once per launch shape and

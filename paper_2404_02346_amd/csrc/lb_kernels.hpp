@@ -7,8 +7,10 @@
 // Population storage is structure-of-arrays: plane i (velocity i) holds the
 // cells row by row, x fastest, rows `pitch` elements apart (pitch is a
 // multiple of 64 elements, so every row starts on a 256-byte boundary for
-// 4-byte storage).  Two state buffers alternate: the step that starts at t
-// reads buffer t & 1 (f^new of step t-1) and writes buffer (t + 1) & 1.
+// 4-byte storage).  Three state buffers rotate: the state entering step t
+// (f^new of step t-1) lives in buffer t mod 3, so a launch that advances one
+// step (t -> t+1) or two steps (t -> t+2) always writes a buffer it does not
+// read.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -137,11 +139,17 @@ struct AccDev {
     int32_t pad;
 };
 
+constexpr int kNumBuf = 3;   // state buffers, indexed by step mod 3
+constexpr int kNumSlot = 4;  // moment boxes and partial sums, indexed by step mod 4
+
+__host__ __device__ inline int buf_of(int64_t t) { return (int)(t % kNumBuf); }
+__host__ __device__ inline int slot_of(int64_t t) { return (int)(t & (kNumSlot - 1)); }
+
 struct InstDev {
     int32_t dim, nx, ny, nz;
     int32_t pitch, xbc;
     int64_t plane;           // elements per population plane
-    void *buf[2];            // state buffers (plane 0)
+    void *buf[kNumBuf];      // state buffers (plane 0)
     double c0sq;             // fluid c0^2 (outside the box)
     int32_t bb_lo[3];        // sound-speed box origin
     int32_t bb_n[3];         // sound-speed box extent (0 -> no box)
@@ -152,10 +160,10 @@ struct InstDev {
     // measurement
     int32_t mb_lo[3];        // moment box origin (cells whose rho, J the surface reads)
     int32_t mb_n[3];         // moment box extent (0 -> no measurement)
-    void *mom[2];            // moment boxes (rho, Jx, Jy, Jz per cell, compute type) by step parity
+    void *mom[kNumSlot];     // moment boxes (rho, Jx, Jy, Jz per cell, compute type) by step mod 4
     int32_t n_surf, n_chunks;  // surface elements, 64-element chunks
     const SurfPt *surf;
-    double *part;            // 2 x n_chunks x 4 per-chunk flux sums by step parity
+    double *part;            // 4 x n_chunks x 4 per-chunk flux sums by step mod 4
     double c0sq_force;       // c0^2 in the surface integral
     double force_scale;      // -1 / (rho0 * scale^2)
     int64_t avg_start;
@@ -165,36 +173,43 @@ struct InstDev {
 };
 
 struct SegInfo {
-    int32_t task0;      // first wave task of the run
+    int32_t task0;      // first wave task of the run (one-step launch)
     int32_t first;      // first (internal) instance of the run
     int32_t nx, ny, nz; // shape shared by the run
     int32_t xsegs;      // wave tasks per row
     int32_t tpi;        // wave tasks per instance
     int32_t pad;
+    int32_t blk0;       // first block of the run (two-step launch)
+    int32_t bpi;        // blocks per instance (two-step launch)
+    int32_t nyb;        // row blocks per instance (two-step launch)
+    int32_t pad2;
 };
 
-// One launch = [reducer blocks][surface blocks][lattice blocks], a
-// three-stage pipeline over consecutive steps:
-//  * lattice blocks advance step t and store rho1, J1 of f(t) in the moment
-//    box of parity t & 1;
-//  * surface blocks interpolate F(t_meas = t - 1) from the moment box of
-//    parity t_meas & 1 and write one partial sum per 64 elements;
-//  * reducer blocks sum the partials of F(t_red = t - 2) in a fixed order,
-//    scale, trace and accumulate.
-// Every stage reads what an earlier launch wrote, so no stage waits on
-// another inside a launch.
-// The lattice step of a launch is t = *tp + dt: the counter lives in device
-// memory so that a captured sequence of launches can be replayed at any t.
+// One launch = [reducer blocks][surface blocks][lattice blocks] (the
+// two-step kernel puts its lattice blocks first), a three-stage pipeline
+// over consecutive steps:
+//  * lattice blocks advance steps t .. t+nst-1 (nst = 1 or 2) and store
+//    rho1, J1 of each f(s) in the moment box of slot s mod 4;
+//  * surface blocks interpolate F(s) for the n_ms steps s = t - meas_off ..
+//    that earlier launches advanced, from their moment boxes, and write one
+//    partial sum per 64 elements into slot s mod 4;
+//  * reducer blocks sum the partials of the n_rs steps t - red_off .. (in
+//    step order, one block per instance) in a fixed order, scale, trace and
+//    accumulate.
+// Every stage reads what an earlier launch wrote, and the slots written and
+// read by one launch differ mod 4, so no stage waits on another inside a
+// launch.  The lattice step of a launch is t = *tp + dt: the counter lives
+// in device memory so that a captured sequence of launches can be replayed
+// at any t.
 struct StepArgs {
     const InstDev *inst;
-    const int64_t *tp;        // device step counter
+    const int64_t *tp;        // device step counter: {t, t mod 3}
     int32_t dt;               // offset of this launch from *tp
-    int32_t meas_off;         // surface stage measures t - meas_off
-    int32_t red_off;          // reducer stage reduces t - red_off
+    int32_t meas_off, n_ms;   // surface stage measures t - meas_off + j, j < n_ms
+    int32_t red_off, n_rs;    // reducer stage reduces t - red_off + j, j < n_rs
     int32_t nseg;
-    int32_t ntask;
-    int32_t n_red, n_sb;
-    int32_t pad;
+    int32_t ntask;            // lattice tasks (one-step launch) or blocks (two-step launch)
+    int32_t n_red, n_sb;      // reducer blocks; surface blocks per measured step
     SegInfo seg[kMaxSeg];
     const int32_t *sb_inst;   // per surface block: internal instance
     const int32_t *sb_chunk;  // per surface block: chunk of 64 elements
@@ -219,8 +234,43 @@ __device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlan
 //   f^new_0    = 2 (1 - dim c^2) rho - f_0,
 // with c = c(x) the local sound speed.
 // ---------------------------------------------------------------------------
+template <int DIM, typename C>
+__device__ inline void cell_rule(const C *f, C rho, C c2, int x, int nx, bool driven, C phi, C rs,
+                                 C *out)
+{
+    constexpr int Q = 2 * DIM + 1;
+    if (driven && (x == 0 || x == nx - 1)) {
+        // damped bounce-back of the pre-collision populations (eq. bounce-back)
+        out[0] = phi * f[0];
+#pragma unroll
+        for (int i = 1; i < Q; i += 2) {
+            out[i] = phi * f[i + 1];
+            out[i + 1] = phi * f[i];
+        }
+    } else if (driven && x == 1) {
+        // imposed density with the cell's own momentum (eq. imposingfields)
+        const C h = (C)0.5;
+        out[0] = rs * ((C)1 - (C)DIM * c2);
+#pragma unroll
+        for (int i = 1; i < Q; i += 2) {
+            const C Ja = f[i] - f[i + 1];
+            out[i] = h * (c2 * rs + Ja);
+            out[i + 1] = h * (c2 * rs - Ja);
+        }
+    } else {
+        const C c2rho = c2 * rho;
+        out[0] = (C)2 * ((C)1 - (C)DIM * c2) * rho - f[0];
+#pragma unroll
+        for (int i = 1; i < Q; i += 2) {
+            out[i] = c2rho - f[i + 1];
+            out[i + 1] = c2rho - f[i];
+        }
+    }
+}
+
 template <int DIM, typename S, int CPL, int XM, int NT>
-__device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task, int lane)
+__device__ inline void lattice_task(const StepArgs &a, const int64_t t, const int bsrc, int task,
+                                    int lane)
 {
     using T = StoreTraits<S>;
     using R = typename T::R;
@@ -254,11 +304,11 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task
     const int mb_lo0 = I.mb_lo[0], mb_lo1 = I.mb_lo[1], mb_lo2 = I.mb_lo[2];
     const int mb_n0 = I.mb_n[0], mb_n1 = I.mb_n[1], mb_n2 = I.mb_n[2];
     const gptr<const C> c2box = to_global<C>(I.c2box);
-    const gptr<C> mom = to_global<C>(I.mom[t & 1]);
+    const gptr<C> mom = to_global<C>(I.mom[slot_of(t)]);
     const C phi = (C)I.wall_phi;
     const double src_amp = I.src_amp, omega = I.omega;
-    const gptr<const R> src = to_global<R>(static_cast<const void *>(I.buf[t & 1]));
-    const gptr<R> dst = to_global<R>(I.buf[(t + 1) & 1]);
+    const gptr<const R> src = to_global<R>(static_cast<const void *>(I.buf[bsrc]));
+    const gptr<R> dst = to_global<R>(I.buf[bsrc == kNumBuf - 1 ? 0 : bsrc + 1]);
 
     const int ym = (y == 0) ? ny - 1 : y - 1;
     const int yp = (y == ny - 1) ? 0 : y + 1;
@@ -377,33 +427,13 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task
         if (x >= nx) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) out[i] = C(0);  // padding stays zero
-        } else if (driven && (x == 0 || x == nx - 1)) {
-            // damped bounce-back of the pre-collision populations (eq. bounce-back)
-            out[0] = phi * f[0][c];
-#pragma unroll
-            for (int i = 1; i < Q; i += 2) {
-                out[i] = phi * f[i + 1][c];
-                out[i + 1] = phi * f[i][c];
-            }
-        } else if (driven && x == 1) {
-            // imposed density with the cell's own momentum (eq. imposingfields)
-            const C rs = (C)(src_amp * sin(omega * (double)t));
-            const C h = (C)0.5;
-            out[0] = rs * ((C)1 - (C)DIM * c2);
-#pragma unroll
-            for (int i = 1; i < Q; i += 2) {
-                const C Ja = f[i][c] - f[i + 1][c];
-                out[i] = h * (c2 * rs + Ja);
-                out[i + 1] = h * (c2 * rs - Ja);
-            }
         } else {
-            const C c2rho = c2 * rho;
-            out[0] = (C)2 * ((C)1 - (C)DIM * c2) * rho - f[0][c];
+            C fc[Q];
 #pragma unroll
-            for (int i = 1; i < Q; i += 2) {
-                out[i] = c2rho - f[i + 1][c];
-                out[i + 1] = c2rho - f[i][c];
-            }
+            for (int i = 0; i < Q; ++i) fc[i] = f[i][c];
+            C rs = C(0);
+            if (driven && x == 1) rs = (C)(src_amp * sin(omega * (double)t));
+            cell_rule<DIM, C>(fc, rho, c2, x, nx, driven, phi, rs, out);
         }
 #pragma unroll
         for (int i = 0; i < Q; ++i) vset<R, CPL>(o[i], c, T::to_r(out[i]));
@@ -412,6 +442,219 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, int task
 #pragma unroll
         for (int i = 0; i < Q; ++i)
             vstore<V, (NT >= 1)>((gptr<V>)at(dst + (i * plane + row), ux), o[i]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two steps per launch (t -> t + 2; D3Q7, driven x sheets, rows of at most
+// 256 cells).  A block covers whole rows: wavefront w moves the cells
+// x = 64 (w % nw) + lane of row group w / nw, with nw = pitch / 64
+// wavefronts per row and 4 / nw row groups (with nw = 3 the fourth
+// wavefront idles but keeps the barriers).  A row group owns R consecutive
+// rows and a chunk of up to kZChunk planes.  It marches through the planes:
+// for plane p it advances step t on its rows plus one halo row on each side
+// (of those only the population moving into the owned rows is kept) and
+// holds the post-collision values in registers; then it finishes step t + 1
+// on plane p - 1, whose seven incoming populations are now all known: the
+// +x / -x ones shifted across lanes (across wavefronts through LDS), +y / -y
+// from the neighbouring rows, +z / -z from planes p - 2 and p.  Per two
+// steps each plane is read about (R + 2) / R times (the halo rows, and the
+// halo planes at the chunk ends, are read twice) and written once, against
+// two reads and two writes for two one-step launches.
+// The per-cell arithmetic is cell_rule, as in lattice_task, and 16-bit
+// storage rounds the step-t values through the storage type, so the state
+// is bit-identical to that of two one-step launches.  Moments of f(t) and
+// f(t + 1) go to their moment boxes as in lattice_task.
+// ---------------------------------------------------------------------------
+constexpr int kZChunk = 32;
+constexpr int kTwoStepMaxPitch = 256;
+
+// A row (y, z) of a box (origin lo, extent n): -1 if the row misses it,
+// else the row's offset in cells.  Uniform over a wavefront.
+__device__ inline int box_row(const int *lo, const int *n, int y, int z)
+{
+    const int by = y - lo[1], bz = z - lo[2];
+    if (n[0] <= 0 || by < 0 || by >= n[1] || bz < 0 || bz >= n[2]) return -1;
+    return (bz * n[1] + by) * n[0];
+}
+
+template <typename C>
+__device__ inline void store_moments(gptr<C> mom, int mrow, int mb_lo0, int mb_n0, int x, C rho,
+                                     const C *f)
+{
+    const int bx = x - mb_lo0;
+    if (mrow >= 0 && bx >= 0 && bx < mb_n0) {
+        using V4 = typename VecT<C, 4>::type;
+        V4 mv;
+        mv[0] = rho;
+        mv[1] = f[1] - f[2];
+        mv[2] = f[3] - f[4];
+        mv[3] = f[5] - f[6];
+        *(gptr<V4>)(mom + 4 * (int64_t)(mrow + bx)) = mv;
+    }
+}
+
+template <typename C>
+__device__ inline C c2_at(gptr<const C> c2box, int crow, int bb_lo0, int bb_n0, C c0sq, int x)
+{
+    const int bx = x - bb_lo0;
+    if (crow >= 0 && bx >= 0 && bx < bb_n0) return c2box[crow + bx];
+    return c0sq;
+}
+
+template <typename S, int R, int NT>
+__device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const int bsrc, int lb,
+                                      typename StoreTraits<S>::C (*xe)[4][R][2])
+{
+    using T = StoreTraits<S>;
+    using E = typename T::R;
+    using C = typename T::C;
+    int s = 0;
+#pragma unroll
+    for (int k = 1; k < kMaxSeg; ++k)
+        if (k < a.nseg && lb >= a.seg[k].blk0) s = k;
+    const SegInfo &sg = a.seg[s];
+    const int local = lb - sg.blk0;
+    const int il = local / sg.bpi;
+    const int rem = local - il * sg.bpi;
+    const int zc = rem / sg.nyb;
+    const int yb = rem - zc * sg.nyb;
+    const auto &I = to_const(a.inst)[sg.first + il];
+    const int nx = sg.nx, ny = sg.ny, nz = sg.nz;
+    const int pitch = I.pitch;
+    const int64_t plane = I.plane;
+    const int nw = pitch / 64;
+    const int ng = 4 / nw;
+    const int lane = threadIdx.x & 63;
+    const int w = wave_uniform(threadIdx.x >> 6);
+    const int g = w / nw, xs = w - g * nw;
+    const bool active = g < ng;
+    const int y0 = (yb * ng + (active ? g : 0)) * R;
+    const int z0 = zc * kZChunk;
+    const int zlen = min(kZChunk, nz - z0);
+    const int x = xs * 64 + lane;
+    const bool xin = active && x < nx;
+    const C c0sq = (C)I.c0sq;
+    const C phi = (C)I.wall_phi;
+    const gptr<const C> c2box = to_global<C>(I.c2box);
+    const bool meas = I.mb_n[0] > 0;
+    const int bb_lo[3] = {I.bb_lo[0], I.bb_lo[1], I.bb_lo[2]};
+    const int bb_n[3] = {I.bb_n[0], I.bb_n[1], I.bb_n[2]};
+    const int mb_lo[3] = {I.mb_lo[0], I.mb_lo[1], I.mb_lo[2]};
+    const int mb_n[3] = {I.mb_n[0], I.mb_n[1], I.mb_n[2]};
+    const gptr<C> mom_a = to_global<C>(I.mom[slot_of(t)]);
+    const gptr<C> mom_b = to_global<C>(I.mom[slot_of(t + 1)]);
+    C rs_a = C(0), rs_b = C(0);
+    if (x == 1) {
+        rs_a = (C)(I.src_amp * sin(I.omega * (double)t));
+        rs_b = (C)(I.src_amp * sin(I.omega * (double)(t + 1)));
+    }
+    const gptr<const E> src = to_global<E>(static_cast<const void *>(I.buf[bsrc]));
+    const gptr<E> dst = to_global<E>(I.buf[bsrc == 0 ? 2 : bsrc - 1]);  // buffer (t + 2) mod 3
+    const uint32_t ux = (uint32_t)x;
+
+    // step-t values of plane p - 1, pull-ready for step t + 1 (owned rows)
+    C Q0[R], Qpx[R], Qmx[R], Qpy[R], Qmy[R], Qpz[R], Qpz2[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) Q0[j] = Qpx[j] = Qmx[j] = Qpy[j] = Qmy[j] = Qpz[j] = Qpz2[j] = C(0);
+
+    for (int p = -1; p <= zlen; ++p) {
+        int zp = z0 + p;
+        zp = (zp < 0) ? zp + nz : (zp >= nz ? zp - nz : zp);
+        const int zm = (zp == 0) ? nz - 1 : zp - 1;
+        const int zn = (zp == nz - 1) ? 0 : zp + 1;
+        const bool own_plane = p >= 0 && p < zlen;
+        const int sl = (p + 2) & 1;
+        C N0[R], Npx[R], Nmx[R], Npy[R], Nmy[R], Npz[R], Nmz[R];
+        C prev_py = C(0);
+#pragma unroll
+        for (int j = -1; j <= R; ++j) {
+            int y = y0 + j;
+            y = (y < 0) ? y + ny : (y >= ny ? y - ny : y);
+            const int ym = (y == 0) ? ny - 1 : y - 1;
+            const int yn = (y == ny - 1) ? 0 : y + 1;
+            C f[7], o[7];
+            if (xin) {
+                const int64_t row = ((int64_t)zp * ny + y) * pitch;
+                f[0] = T::to_c(*at(src + row, ux));
+                f[1] = T::to_c(*at(src + plane + row - 1, ux));
+                f[2] = T::to_c(*at(src + 2 * plane + row + 1, ux));
+                f[3] = T::to_c(*at(src + 3 * plane + ((int64_t)zp * ny + ym) * pitch, ux));
+                f[4] = T::to_c(*at(src + 4 * plane + ((int64_t)zp * ny + yn) * pitch, ux));
+                f[5] = T::to_c(*at(src + 5 * plane + ((int64_t)zm * ny + y) * pitch, ux));
+                f[6] = T::to_c(*at(src + 6 * plane + ((int64_t)zn * ny + y) * pitch, ux));
+                if (x == 0) f[1] = C(0);       // nothing enters from outside the sheets
+                if (x == nx - 1) f[2] = C(0);
+                C rho = f[0];
+#pragma unroll
+                for (int i = 1; i < 7; ++i) rho += f[i];
+                if (meas && own_plane && j >= 0 && j < R)
+                    store_moments(mom_a, box_row(mb_lo, mb_n, y, zp), mb_lo[0], mb_n[0], x, rho, f);
+                const C c2 = c2_at(c2box, box_row(bb_lo, bb_n, y, zp), bb_lo[0], bb_n[0], c0sq, x);
+                cell_rule<3, C>(f, rho, c2, x, nx, true, phi, rs_a, o);
+#pragma unroll
+                for (int i = 0; i < 7; ++i) o[i] = T::to_c(T::to_r(o[i]));
+            } else {
+#pragma unroll
+                for (int i = 0; i < 7; ++i) o[i] = C(0);
+            }
+            if (j >= 0 && j < R) {
+                N0[j] = o[0];
+                Npx[j] = __shfl_up(o[1], 1);    // +x arrives from x - 1
+                Nmx[j] = __shfl_down(o[2], 1);  // -x arrives from x + 1
+                if (lane == 63) xe[sl][w][j][0] = o[1];
+                if (lane == 0) xe[sl][w][j][1] = o[2];
+                Npy[j] = prev_py;               // +y arrives from row j - 1
+                Npz[j] = o[5];
+                Nmz[j] = o[6];
+            }
+            if (j >= 1) Nmy[j - 1] = o[4];      // -y arrives from row j + 1
+            prev_py = o[3];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            // neighbours in the same row group only (an idle wavefront reads nothing)
+            if (lane == 0) Npx[j] = (active && xs > 0) ? xe[sl][w - 1][j][0] : C(0);
+            if (lane == 63) Nmx[j] = (active && xs < nw - 1) ? xe[sl][w + 1][j][1] : C(0);
+        }
+        if (p >= 1 && xin) {
+            // step t + 1 on plane zq = z0 + p - 1
+            const int zq = z0 + p - 1;
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int y = y0 + j;
+                C f[7], o[7];
+                f[0] = Q0[j];
+                f[1] = (x == 0) ? C(0) : Qpx[j];
+                f[2] = (x == nx - 1) ? C(0) : Qmx[j];
+                f[3] = Qpy[j];
+                f[4] = Qmy[j];
+                f[5] = Qpz2[j];  // +z of plane zq - 1
+                f[6] = Nmz[j];   // -z of plane zq + 1
+                C rho = f[0];
+#pragma unroll
+                for (int i = 1; i < 7; ++i) rho += f[i];
+                if (meas)
+                    store_moments(mom_b, box_row(mb_lo, mb_n, y, zq), mb_lo[0], mb_n[0], x, rho, f);
+                const C c2 = c2_at(c2box, box_row(bb_lo, bb_n, y, zq), bb_lo[0], bb_n[0], c0sq, x);
+                cell_rule<3, C>(f, rho, c2, x, nx, true, phi, rs_b, o);
+                const int64_t row = ((int64_t)zq * ny + y) * pitch;
+#pragma unroll
+                for (int i = 0; i < 7; ++i)
+                    vstore<E, (NT >= 1)>(at(dst + (i * plane + row), ux), T::to_r(o[i]));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            Qpz2[j] = Qpz[j];
+            Q0[j] = N0[j];
+            Qpx[j] = Npx[j];
+            Qmx[j] = Nmx[j];
+            Qpy[j] = Npy[j];
+            Qmy[j] = Nmy[j];
+            Qpz[j] = Npz[j];
+        }
     }
 }
 
@@ -436,7 +679,7 @@ __device__ inline void surface_block(const StepArgs &a, const int64_t t_meas, in
     const int chunk = a.sb_chunk[sb];
     const int k = chunk * 64 + lane;
     const bool live = k < I.n_surf;
-    const gptr<const C> mom = to_global<C>(static_cast<const void *>(I.mom[t_meas & 1]));
+    const gptr<const C> mom = to_global<C>(static_cast<const void *>(I.mom[slot_of(t_meas)]));
     const int mbx = I.mb_n[0], mby = I.mb_n[1];
 
     double rI = 0.0, Jx = 0.0, Jy = 0.0, Jz = 0.0;
@@ -484,76 +727,127 @@ __device__ inline void surface_block(const StepArgs &a, const int64_t t_meas, in
         fz += __shfl_xor(fz, off);
     }
     if (lane == 0) {
-        double *o = I.part + ((t_meas & 1) * I.n_chunks + chunk) * 4;
+        double *o = I.part + (slot_of(t_meas) * I.n_chunks + chunk) * 4;
         o[0] = fx;
         o[1] = fy;
         o[2] = fz;
     }
 }
 
-// Reducer: F(t_red) of one instance from its chunk partials (written by the
-// previous launch), scaled, traced and accumulated.
-__device__ inline void reduce_block(const StepArgs &a, const int64_t t, int ii)
+// Reducer: F(t) of one instance for the steps t0 .. t0+n-1 in order, each
+// from its chunk partials (written by an earlier launch), scaled, traced and
+// accumulated.  One block per instance, so the accumulation order is fixed.
+__device__ inline void reduce_block(const StepArgs &a, const int64_t t0, int n, int ii)
 {
     if (threadIdx.x != 0) return;
     const InstDev &I = a.inst[ii];
     if (I.n_surf == 0) return;
-    if (I.max_steps > 0 && t >= I.max_steps) return;
-    const double *p = I.part + (t & 1) * I.n_chunks * 4;
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-    for (int c = 0; c < I.n_chunks; ++c) {
-        s0 += p[4 * c];
-        s1 += p[4 * c + 1];
-        s2 += p[4 * c + 2];
+    for (int j = 0; j < n; ++j) {
+        const int64_t t = t0 + j;
+        if (I.max_steps > 0 && t >= I.max_steps) return;
+        const double *p = I.part + slot_of(t) * I.n_chunks * 4;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        for (int c = 0; c < I.n_chunks; ++c) {
+            s0 += p[4 * c];
+            s1 += p[4 * c + 1];
+            s2 += p[4 * c + 2];
+        }
+        const double F[3] = {s0 * I.force_scale, s1 * I.force_scale, s2 * I.force_scale};
+        if (t < I.trace_cap) {
+            I.trace[3 * t + 0] = F[0];
+            I.trace[3 * t + 1] = F[1];
+            I.trace[3 * t + 2] = F[2];
+        }
+        if (t >= I.avg_start) {
+            AccDev *acc = I.acc;
+            acc->sum[0] += F[0];
+            acc->sum[1] += F[1];
+            acc->sum[2] += F[2];
+            acc->n += 1;
+            if (!(isfinite(F[0]) && isfinite(F[1]) && isfinite(F[2]))) acc->nan = 1;
+        }
     }
-    const double F[3] = {s0 * I.force_scale, s1 * I.force_scale, s2 * I.force_scale};
-    if (t < I.trace_cap) {
-        I.trace[3 * t + 0] = F[0];
-        I.trace[3 * t + 1] = F[1];
-        I.trace[3 * t + 2] = F[2];
+}
+
+// The measurement blocks of a launch (reducers, then the surface blocks of
+// each measured step); returns false for a lattice block.
+template <int DIM, typename C>
+__device__ inline bool measure_part(const StepArgs &a, const int64_t t, int b, double (*lds)[64][4])
+{
+    if (b < a.n_red) {
+        reduce_block(a, t - a.red_off, a.n_rs, b);
+        return true;
     }
-    if (t >= I.avg_start) {
-        AccDev *acc = I.acc;
-        acc->sum[0] += F[0];
-        acc->sum[1] += F[1];
-        acc->sum[2] += F[2];
-        acc->n += 1;
-        if (!(isfinite(F[0]) && isfinite(F[1]) && isfinite(F[2]))) acc->nan = 1;
+    b -= a.n_red;
+    if (b < a.n_ms * a.n_sb) {
+        const int j = b / a.n_sb;
+        const int sb = b - j * a.n_sb;
+        const InstDev &I = a.inst[a.sb_inst[sb]];
+        const int64_t t_meas = t - a.meas_off + j;
+        if (I.max_steps > 0 && t_meas >= I.max_steps) return true;
+        surface_block<DIM, C>(a, t_meas, sb, lds);
+        return true;
     }
+    return false;
 }
 
 template <int DIM, typename S, int CPL, int XM, int NT>
 __global__ void __launch_bounds__(kStepThreads) step_kernel(StepArgs a)
 {
     __shared__ double lds[4][64][4];
-    const int64_t t = *a.tp + a.dt;
+    const int64_t t = a.tp[0] + a.dt;
     const int b = blockIdx.x;
-    if (b < a.n_red) {
-        reduce_block(a, t - a.red_off, b);
-        return;
-    }
-    if (b < a.n_red + a.n_sb) {
-        const int sb = b - a.n_red;
-        const InstDev &I = a.inst[a.sb_inst[sb]];
-        const int64_t t_meas = t - a.meas_off;
-        if (I.max_steps > 0 && t_meas >= I.max_steps) return;
-        surface_block<DIM, typename StoreTraits<S>::C>(a, t_meas, sb, lds);
-        return;
-    }
+    if (measure_part<DIM, typename StoreTraits<S>::C>(a, t, b, lds)) return;
+    const int bsrc = ((int)a.tp[1] + a.dt) % kNumBuf;  // t mod 3 without 64-bit division
     const int wave = wave_uniform(threadIdx.x >> 6);
-    const int task = (b - a.n_red - a.n_sb) * (kStepThreads / 64) + wave;
+    const int task = (b - a.n_red - a.n_ms * a.n_sb) * (kStepThreads / 64) + wave;
     if (task >= a.ntask) return;
-    lattice_task<DIM, S, CPL, XM, NT>(a, t, task, threadIdx.x & 63);
+    lattice_task<DIM, S, CPL, XM, NT>(a, t, bsrc, task, threadIdx.x & 63);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs (each with its own L2):
+// physical block b runs on XCD b % 8.  Give each XCD a contiguous range of
+// the n logical blocks, so that neighbouring row blocks, which read each
+// other's halo rows, share an L2.  A bijection on [0, n).
+constexpr int kNumXcd = 8;
+__device__ inline int xcd_block(int b, int n)
+{
+    const int q = n / kNumXcd, r = n % kNumXcd;
+    const int x = b % kNumXcd, k = b / kNumXcd;
+    return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
+template <typename S, int R, int NT>
+__global__ void __launch_bounds__(kStepThreads) step2_kernel(StepArgs a)
+{
+    using C = typename StoreTraits<S>::C;
+    __shared__ double lds[4][64][4];
+    __shared__ C xe[2][4][R][2];
+    const int64_t t = a.tp[0] + a.dt;
+    const int b = blockIdx.x;
+    // the long lattice blocks first, the short measurement blocks fill the tail
+    if (b < a.ntask) {
+        lattice2_block<S, R, NT>(a, t, ((int)a.tp[1] + a.dt) % kNumBuf, xcd_block(b, a.ntask), xe);
+        return;
+    }
+    measure_part<3, C>(a, t, b - a.ntask, lds);
 }
 
 // Device step counter: set, or advance after a replayed sequence.
+// The counter holds {t, t mod 3} (the phase saves the kernels a 64-bit division).
 __global__ void set_step_kernel(int64_t *tp, int64_t v)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *tp = v;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        tp[0] = v;
+        tp[1] = v % kNumBuf;
+    }
 }
 __global__ void advance_step_kernel(int64_t *tp, int64_t k)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *tp = *tp + k;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        tp[0] = tp[0] + k;
+        tp[1] = (tp[1] + k) % kNumBuf;
+    }
 }
 
 // Fill with zeros (used instead of hipMemsetAsync so that every node of a

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -318,7 +319,7 @@ struct InstPlan {
     int pitch;
     int64_t plane;
     int n_chunks;
-    size_t off_surf, off_part, off_mom[2], off_trace, off_box, off_buf[2];
+    size_t off_surf, off_part, off_mom[kNumSlot], off_trace, off_box, off_buf[kNumBuf];
 };
 
 struct Layout {
@@ -340,7 +341,7 @@ Layout plan(const lb_wave_desc *descs, int n)
     L.off_sbtab = off;
     off = align_up(off + sizeof(int32_t) * 2 * (size_t)L.n_sb_total);
     L.off_tdev = off;
-    off = align_up(off + sizeof(int64_t));
+    off = align_up(off + 2 * sizeof(int64_t));
     L.p.resize(n);
     for (int i = 0; i < n; ++i) {
         const lb_wave_desc &d = descs[i];
@@ -351,19 +352,19 @@ Layout plan(const lb_wave_desc *descs, int n)
         P.plane = plane_stride((int64_t)P.pitch * d.ny * d.nz, elem_bytes(d.storage));
         P.n_chunks = (d.n_surf + 63) / 64;
         P.mbox = measure_box(d);
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < kNumSlot; ++b) {
             P.off_mom[b] = off;
             off = align_up(off + 4 * compute_bytes(d.storage) * P.mbox.cells());
         }
         P.off_surf = off;
         off = align_up(off + sizeof(SurfPt) * d.n_surf);
         P.off_part = off;
-        off = align_up(off + sizeof(double) * 2 * 4 * (size_t)P.n_chunks);
+        off = align_up(off + sizeof(double) * kNumSlot * 4 * (size_t)P.n_chunks);
         P.off_trace = off;
         off = align_up(off + sizeof(double) * 3 * (size_t)d.trace_steps);
         P.off_box = off;
         off = align_up(off + compute_bytes(d.storage) * P.box.cells());
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < kNumBuf; ++b) {
             P.off_buf[b] = off;
             off = align_up(off + elem_bytes(d.storage) * (size_t)P.plane * Q);
         }
@@ -417,6 +418,9 @@ inline void store_host(uint8_t *p, int storage, double v)
 
 struct lb_wave {
     int n = 0, dim = 0, storage = 0, vx = 1, xm = 0, nt = 0;
+    int fused = 1;                    // lattice steps per launch (1 or 2)
+    bool fused_ok = false;            // every instance fits the two-step kernel
+    std::vector<int> blk0;            // internal order, size n + 1: two-step blocks
     char *ws = nullptr;
     size_t ws_bytes = 0;
     hipStream_t stream = nullptr;
@@ -438,12 +442,12 @@ struct lb_wave {
     int64_t meas = 0;                 // steps whose chunk partials exist
     int64_t red = 0;                  // steps reduced into the accumulators
     bool nan_seen = false;
-    int64_t *d_t = nullptr;           // device step counter
+    int64_t *d_t = nullptr;           // device step counter {t, t mod 3}
     int64_t tdev = 0;                 // its value in stream order
     int graph_chunk = 0;              // replay steady steps as captured graphs of this length
     hipStream_t cap_stream = nullptr; // private stream used only for capture
     struct GraphEntry {
-        int k, na, n_red, n_sb;
+        int k, na, n_red, n_sb, nst;
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
@@ -533,15 +537,39 @@ void launch(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
     }
 }
 
-// Measurement part of the launch for step t_launch: partials of F(t_launch - 1)
-// if that state's moments exist and it has not been measured, reduction of
-// the oldest measured step whose partials came from an earlier launch.
+// Rows per row group of the two-step kernel (FP64 holds twice the registers).
+int two_step_rows(int storage) { return storage == LB_F64 ? 2 : 4; }
+
+template <typename S, int R>
+void launch2_t(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
+{
+    if (h->nt == 0)
+        hipLaunchKernelGGL((step2_kernel<S, R, 0>), dim3(blocks), dim3(kStepThreads), 0, st, a);
+    else
+        hipLaunchKernelGGL((step2_kernel<S, R, 1>), dim3(blocks), dim3(kStepThreads), 0, st, a);
+}
+
+void launch2(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
+{
+    if (blocks <= 0) return;
+    switch (h->storage) {
+    case LB_F64: launch2_t<double, 2>(h, a, blocks, st); break;
+    case LB_F32: launch2_t<float, 4>(h, a, blocks, st); break;
+    case LB_F16: launch2_t<_Float16, 4>(h, a, blocks, st); break;
+    default: launch2_t<bf16, 4>(h, a, blocks, st); break;
+    }
+}
+
+// Measurement part of the launch whose lattice part starts at t_launch:
+// reduce every measured step whose partials an earlier launch wrote
+// (steps red .. meas-1), and measure every step whose moments an earlier
+// launch stored (steps meas .. t_launch-1).  A launch advances at most two
+// steps, so both ranges hold at most two steps and the slots they use
+// (step mod 4) differ from those the launch writes.
 void plan_measure(lb_wave *h, StepArgs &a, int64_t t_launch)
 {
-    a.n_red = 0;
-    a.n_sb = 0;
-    a.meas_off = 1;
-    a.red_off = 2;
+    a.n_red = a.n_sb = a.n_ms = a.n_rs = 0;
+    a.meas_off = a.red_off = 0;
     a.sb_inst = h->d_sb_inst;
     a.sb_chunk = h->d_sb_chunk;
     if (!h->any_surf) {
@@ -550,42 +578,52 @@ void plan_measure(lb_wave *h, StepArgs &a, int64_t t_launch)
     }
     if (h->red < h->meas) {
         a.red_off = (int32_t)(t_launch - h->red);
+        a.n_rs = (int32_t)(h->meas - h->red);
         a.n_red = prefix_alive(h, h->red);
-        h->red++;
+        h->red = h->meas;
     }
-    const int64_t newest = t_launch - 1;
-    if (newest >= 0 && h->meas == newest) {
-        a.n_sb = h->sb_first[prefix_alive(h, newest)];
-        h->meas++;
+    if (h->meas < t_launch) {
+        a.meas_off = (int32_t)(t_launch - h->meas);
+        a.n_ms = (int32_t)(t_launch - h->meas);
+        a.n_sb = h->sb_first[prefix_alive(h, h->meas)];
+        h->meas = t_launch;
     }
 }
 
-// Fill the lattice part of `a` for step t (segments of the live prefix) and
-// launch, one launch per kMaxSeg segments; the measurement blocks ride on
-// the first launch.
-void emit_step(const lb_wave *h, StepArgs a, int64_t t, int32_t dt, hipStream_t st)
+// Fill the lattice part of `a` for the steps t .. t+nst-1 (segments of the
+// live prefix) and launch, one launch per kMaxSeg segments; the measurement
+// blocks ride on the first launch.  nst = 1: wave tasks of step_kernel;
+// nst = 2: blocks of step2_kernel (the live prefix is the same for both steps).
+void emit_step(const lb_wave *h, StepArgs a, int64_t t, int32_t dt, int nst, hipStream_t st)
 {
     const int na = active_prefix(h, t);
-    const int ntask_active = h->task0[na];
+    const bool two = nst == 2;
+    auto first_of = [&](const SegInfo &sg) { return two ? sg.blk0 : sg.task0; };
+    const int n_active = two ? h->blk0[na] : h->task0[na];
     a.dt = dt;
     size_t s = 0;
     bool first = true;
     do {
-        const int base = s < h->segs.size() ? h->segs[s].task0 : 0;
+        const int base = s < h->segs.size() ? first_of(h->segs[s]) : 0;
         int k = 0;
-        for (; k < kMaxSeg && s + k < h->segs.size() && h->segs[s + k].task0 < ntask_active; ++k) {
+        for (; k < kMaxSeg && s + k < h->segs.size() && first_of(h->segs[s + k]) < n_active; ++k) {
             a.seg[k] = h->segs[s + k];
-            a.seg[k].task0 -= base;
+            a.seg[k].task0 -= two ? 0 : base;
+            a.seg[k].blk0 -= two ? base : 0;
         }
-        const int end = (s + k < h->segs.size()) ? std::min(h->segs[s + k].task0, ntask_active)
-                                                 : ntask_active;
+        const int end = (s + k < h->segs.size()) ? std::min(first_of(h->segs[s + k]), n_active)
+                                                 : n_active;
         a.nseg = k;
         a.ntask = k > 0 ? end - base : 0;
-        if (!first) a.n_red = a.n_sb = 0;
-        launch(h, a, a.n_red + a.n_sb + (a.ntask + 3) / 4, st);
+        if (!first) a.n_red = a.n_sb = a.n_ms = a.n_rs = 0;
+        const int meas_blocks = a.n_red + a.n_ms * a.n_sb;
+        if (two)
+            launch2(h, a, meas_blocks + a.ntask, st);
+        else
+            launch(h, a, meas_blocks + (a.ntask + 3) / 4, st);
         first = false;
         s += k;
-    } while (s < h->segs.size() && h->segs[s].task0 < ntask_active);
+    } while (s < h->segs.size() && first_of(h->segs[s]) < n_active);
 }
 
 // Make the device counter equal `t` in stream order if dt would not fit.
@@ -597,9 +635,9 @@ void sync_counter(lb_wave *h, int64_t t)
     }
 }
 
-// One lattice step for every live instance, with the measurement of the
-// previous steps folded into the same launch.
-int enqueue_step(lb_wave *h)
+// nst lattice steps (1 or 2) for every live instance, with the measurement
+// of the previous steps folded into the same launch.
+int enqueue_step(lb_wave *h, int nst)
 {
     const int64_t t = h->t;
     sync_counter(h, t);
@@ -608,10 +646,16 @@ int enqueue_step(lb_wave *h)
     a.inst = h->d_inst;
     a.tp = h->d_t;
     plan_measure(h, a, t);
-    emit_step(h, a, t, (int32_t)(t - h->tdev), h->stream);
+    emit_step(h, a, t, (int32_t)(t - h->tdev), nst, h->stream);
     HIP_TRY(hipGetLastError());
-    h->t++;
+    h->t += nst;
     return LB_OK;
+}
+
+// Steps t and t+1 can share a two-step launch: no instance stops after t.
+bool can_fuse(const lb_wave *h)
+{
+    return h->fused == 2 && active_prefix(h, h->t) == active_prefix(h, h->t + 1);
 }
 
 // Finish the measurement of every completed step (two launches at most).
@@ -625,21 +669,24 @@ int flush_measure(lb_wave *h)
         a.tp = h->d_t;
         a.dt = (int32_t)(h->t - h->tdev);
         plan_measure(h, a, h->t);
-        launch(h, a, a.n_red + a.n_sb, h->stream);
+        launch(h, a, a.n_red + a.n_ms * a.n_sb, h->stream);
         HIP_TRY(hipGetLastError());
     }
     return LB_OK;
 }
 
-// Steps t .. t+k-1 all launch the same blocks: the measurement runs one and
-// two steps behind and no instance stops inside the window.
+// Steps t .. t+k-1 all launch the same blocks (k / nst launches of nst
+// steps): the measurement runs nst and 2 nst steps behind and no instance
+// stops inside the window.
 bool steady(const lb_wave *h, int64_t k)
 {
     const int64_t t = h->t;
-    if (h->any_surf && (t < 2 || h->meas != t - 1 || h->red != t - 2)) return false;
+    const int nst = h->fused;
+    if (k % nst) return false;
+    if (h->any_surf && (t < 2 * nst || h->meas != t - nst || h->red != t - 2 * nst)) return false;
     for (const InstDev &I : h->hinst) {
         const int64_t ms = I.max_steps;
-        if (ms > 0 && ms > t - 2 && ms < t + k) return false;
+        if (ms > 0 && ms > t - 2 * nst && ms < t + k) return false;
     }
     return true;
 }
@@ -649,12 +696,14 @@ bool steady(const lb_wave *h, int64_t k)
 int replay_steps(lb_wave *h, int k)
 {
     const int64_t t = h->t;
+    const int nst = h->fused;
     const int na = active_prefix(h, t);
-    const int n_red = h->any_surf ? prefix_alive(h, t - 2) : 0;
-    const int n_sb = h->any_surf ? h->sb_first[prefix_alive(h, t - 1)] : 0;
+    const int n_red = h->any_surf ? prefix_alive(h, t - 2 * nst) : 0;
+    const int n_sb = h->any_surf ? h->sb_first[prefix_alive(h, t - nst)] : 0;
     hipGraphExec_t exec = nullptr;
     for (auto &g : h->graphs)
-        if (g.k == k && g.na == na && g.n_red == n_red && g.n_sb == n_sb) exec = g.exec;
+        if (g.k == k && g.na == na && g.n_red == n_red && g.n_sb == n_sb && g.nst == nst)
+            exec = g.exec;
     if (!exec) {
         if (!h->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
         HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
@@ -662,13 +711,15 @@ int replay_steps(lb_wave *h, int k)
         std::memset(&a, 0, sizeof a);
         a.inst = h->d_inst;
         a.tp = h->d_t;
-        a.meas_off = 1;
-        a.red_off = 2;
+        a.meas_off = nst;
+        a.n_ms = h->any_surf ? nst : 0;
+        a.red_off = 2 * nst;
+        a.n_rs = h->any_surf ? nst : 0;
         a.n_red = n_red;
         a.n_sb = n_sb;
         a.sb_inst = h->d_sb_inst;
         a.sb_chunk = h->d_sb_chunk;
-        for (int j = 0; j < k; ++j) emit_step(h, a, t + j, j, h->cap_stream);
+        for (int j = 0; j < k; j += nst) emit_step(h, a, t + j, j, nst, h->cap_stream);
         hipLaunchKernelGGL(advance_step_kernel, dim3(1), dim3(64), 0, h->cap_stream, h->d_t,
                            (int64_t)k);
         hipGraph_t graph = nullptr;
@@ -677,7 +728,7 @@ int replay_steps(lb_wave *h, int k)
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (e != hipSuccess) return fail(LB_EDEVICE, "graph instantiate: %s", hipGetErrorString(e));
-        h->graphs.push_back({k, na, n_red, n_sb, exec});
+        h->graphs.push_back({k, na, n_red, n_sb, nst, exec});
     }
     if (h->tdev != t) {
         hipLaunchKernelGGL(set_step_kernel, dim3(1), dim3(64), 0, h->stream, h->d_t, t);
@@ -718,7 +769,7 @@ int zero_state(lb_wave *h)
         const InstPlan &P = h->lay.p[i];
         const lb_wave_desc &d = h->desc[i];
         const size_t buf = elem_bytes(d.storage) * (size_t)P.plane * (2 * d.dim + 1);
-        for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < kNumBuf; ++b) {
             int st = zero_region(h, P.off_buf[b], buf);
             if (st) return st;
         }
@@ -828,8 +879,7 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
         I.pitch = P.pitch;
         I.xbc = d.xbc;
         I.plane = P.plane;
-        I.buf[0] = h->ws + P.off_buf[0];
-        I.buf[1] = h->ws + P.off_buf[1];
+        for (int b = 0; b < kNumBuf; ++b) I.buf[b] = h->ws + P.off_buf[b];
         I.c0sq = d.c0 * d.c0;
         for (int a = 0; a < 3; ++a) {
             I.bb_lo[a] = P.box.lo[a];
@@ -846,8 +896,7 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
             I.mb_lo[a] = P.mbox.lo[a];
             I.mb_n[a] = P.mbox.n[a];
         }
-        I.mom[0] = h->ws + P.off_mom[0];
-        I.mom[1] = h->ws + P.off_mom[1];
+        for (int b = 0; b < kNumSlot; ++b) I.mom[b] = h->ws + P.off_mom[b];
         I.n_surf = d.n_surf;
         I.n_chunks = P.n_chunks;
         I.surf = reinterpret_cast<const SurfPt *>(h->ws + P.off_surf);
@@ -917,6 +966,25 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
         host_blobs.push_back(std::move(blob));
         blob_off.push_back(L.off_sbtab);
     }
+    // two-step decomposition: row groups of R rows, 4 / nw groups per block,
+    // chunks of kZChunk planes
+    {
+        const int R = two_step_rows(h->storage);
+        h->fused_ok = (h->dim == 3);
+        h->blk0.assign(n_inst + 1, 0);
+        for (int ii = 0; ii < n_inst; ++ii) {
+            const InstDev &I = h->hinst[ii];
+            int bpi = 0;
+            if (I.xbc == 0 && I.pitch <= kTwoStepMaxPitch) {
+                const int ng = 4 / (I.pitch / 64);
+                if (I.ny % (R * ng) == 0)
+                    bpi = (I.ny / (R * ng)) * ((I.nz + kZChunk - 1) / kZChunk);
+            }
+            if (bpi == 0) h->fused_ok = false;
+            h->blk0[ii + 1] = h->blk0[ii] + bpi;
+        }
+        if (!h->fused_ok) std::fill(h->blk0.begin(), h->blk0.end(), 0);
+    }
     // segments: maximal runs of equal shape in internal order
     for (int ii = 0; ii < n_inst; ++ii) {
         const InstDev &I = h->hinst[ii];
@@ -931,6 +999,12 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
             sg.nz = I.nz;
             sg.xsegs = (I.nx + 63) / 64;
             sg.tpi = sg.xsegs * I.ny * I.nz;
+            sg.blk0 = h->blk0[ii];
+            sg.bpi = h->blk0[ii + 1] - h->blk0[ii];
+            if (h->fused_ok) {
+                const int ng = 4 / (I.pitch / 64);
+                sg.nyb = I.ny / (two_step_rows(h->storage) * ng);
+            }
             h->segs.push_back(sg);
         }
     }
@@ -966,13 +1040,36 @@ int lb_wave_step_n(lb_wave *h, int64_t n_steps)
         if (k >= 2 && left >= k && steady(h, k)) {
             st = replay_steps(h, k);
             left -= k;
+        } else if (left >= 2 && can_fuse(h)) {
+            st = enqueue_step(h, 2);
+            left -= 2;
         } else {
-            st = enqueue_step(h);
+            st = enqueue_step(h, 1);
             left -= 1;
         }
         if (st != LB_OK) return st;
     }
     return flush_measure(h);
+}
+
+int lb_wave_set_steps_per_launch(lb_wave *h, int32_t k)
+{
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (k != 1 && k != 2) return fail(LB_EINVAL, "steps per launch must be 1 or 2");
+    if (k == 2 && !h->fused_ok)
+        return fail(LB_EINVAL, "two steps per launch need 3D instances with driven x sheets, "
+                               "nx <= %d and ny a multiple of the row block",
+                    kTwoStepMaxPitch);
+    if (k != h->fused) drop_graphs(h);
+    h->fused = k;
+    return LB_OK;
+}
+
+int lb_wave_get_steps_per_launch(const lb_wave *h, int32_t *k)
+{
+    if (!h || !k) return fail(LB_EINVAL, "NULL argument");
+    *k = h->fused;
+    return LB_OK;
 }
 
 int lb_wave_set_graph(lb_wave *h, int32_t chunk)
@@ -1032,8 +1129,7 @@ int lb_wave_state_view(const lb_wave *h, int32_t inst, lb_state_view *v)
     if (inst < 0 || inst >= h->n) return fail(LB_EINVAL, "instance out of range");
     const int ii = h->pos[inst];
     const InstPlan &P = h->lay.p[inst];
-    const int b = (int)(steps_of(h, ii) & 1);
-    v->offset_bytes = P.off_buf[b];
+    v->offset_bytes = P.off_buf[buf_of(steps_of(h, ii))];
     v->plane_bytes = elem_bytes(h->storage) * (size_t)P.plane;
     v->pitch = P.pitch;
     v->elem_bytes = (int32_t)elem_bytes(h->storage);
@@ -1163,33 +1259,46 @@ int lb_wave_autotune(lb_wave *h, int32_t n_trial, double *best_ms)
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     double best = 1e300;
-    int bv[3] = {1, 0, 0};
+    int bv[4] = {1, 0, 0, 1};  // cells per lane, x mode, nontemporal, steps per launch
     const int xm_max = elem_bytes(h->storage) >= 4 ? 1 : 0;
+    const int trial = n_trial + (n_trial & 1);  // even, so two-step launches cover it
+    auto time_it = [&](double *per) -> int {
+        int st = lb_wave_step_n(h, 2);  // warm-up
+        if (st) return st;
+        HIP_TRY(hipEventRecord(e0, h->stream));
+        st = lb_wave_step_n(h, trial);
+        if (st) return st;
+        HIP_TRY(hipEventRecord(e1, h->stream));
+        HIP_TRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+        *per = ms / trial;
+        return LB_OK;
+    };
+    std::vector<std::array<int, 4>> cand;
     for (int cpl : {1, 2, 4})
         for (int xm = 0; xm <= xm_max; ++xm)
-            for (int nt = 0; nt <= 2; ++nt) {
-                int st = lb_wave_set_variant(h, cpl, xm, nt);
-                if (st) return st;
-                st = lb_wave_step_n(h, 2);  // warm-up
-                if (st) return st;
-                HIP_TRY(hipEventRecord(e0, h->stream));
-                st = lb_wave_step_n(h, n_trial);
-                if (st) return st;
-                HIP_TRY(hipEventRecord(e1, h->stream));
-                HIP_TRY(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-                const double per = ms / n_trial;
-                if (per < best) {
-                    best = per;
-                    bv[0] = cpl;
-                    bv[1] = xm;
-                    bv[2] = nt;
-                }
-            }
+            for (int nt = 0; nt <= 2; ++nt) cand.push_back({cpl, xm, nt, 1});
+    if (h->fused_ok)
+        for (int nt = 0; nt <= 1; ++nt) cand.push_back({1, xm_max, nt, 2});
+    for (const auto &c : cand) {
+        int st = lb_wave_set_steps_per_launch(h, c[3]);
+        if (st) return st;
+        st = lb_wave_set_variant(h, c[0], c[1], c[2]);
+        if (st) return st;
+        double per = 0.0;
+        st = time_it(&per);
+        if (st) return st;
+        if (per < best) {
+            best = per;
+            for (int i = 0; i < 4; ++i) bv[i] = c[i];
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    int st = lb_wave_set_variant(h, bv[0], bv[1], bv[2]);
+    int st = lb_wave_set_steps_per_launch(h, bv[3]);
+    if (st) return st;
+    st = lb_wave_set_variant(h, bv[0], bv[1], bv[2]);
     if (st) return st;
     if (best_ms) *best_ms = best;
     st = zero_state(h);

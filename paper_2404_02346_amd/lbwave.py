@@ -79,6 +79,8 @@ def lib():
                                           C.POINTER(C.c_int32)]
         L.lb_wave_set_tile.argtypes = [vp, C.c_int32]
         L.lb_wave_set_graph.argtypes = [vp, C.c_int32]
+        L.lb_wave_set_steps_per_launch.argtypes = [vp, C.c_int32]
+        L.lb_wave_get_steps_per_launch.argtypes = [vp, C.POINTER(C.c_int32)]
         L.lb_wave_get_tile.argtypes = [vp, C.POINTER(C.c_int32)]
         L.lb_wave_autotune.argtypes = [vp, C.c_int32, _dp]
         L.lb_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
@@ -258,6 +260,15 @@ class LBWave:
 
     def set_graph(self, chunk: int):
         _check(lib().lb_wave_set_graph(self._h, int(chunk)))
+
+    def set_steps_per_launch(self, k: int):
+        """1: one lattice step per launch; 2: the fused two-step kernel (3D, driven sheets)."""
+        _check(lib().lb_wave_set_steps_per_launch(self._h, int(k)))
+
+    def steps_per_launch(self) -> int:
+        v = C.c_int32()
+        _check(lib().lb_wave_get_steps_per_launch(self._h, C.byref(v)))
+        return v.value
 
     def tile(self) -> int:
         v = C.c_int32()
