@@ -365,7 +365,10 @@ def main():
 
     # --- plain single-instance rate for the forces/s comparison ---
     one = P.LBWave([probs[7]], storage=args.storage, stream=stream)
-    set_variant(one, variant)
+    if fixed:
+        set_variant(one, fixed)
+    else:
+        one.autotune(4)  # one box alone: its own best variant
     one.set_graph(args.graph)
     one.step(10)
     torch.cuda.synchronize()

@@ -210,6 +210,8 @@ struct StepArgs {
     int32_t nseg;
     int32_t ntask;            // lattice tasks (one-step launch) or blocks (two-step launch)
     int32_t n_red, n_sb;      // reducer blocks; surface blocks per measured step
+    int32_t zchunk;           // planes per row-group chunk (two-step launch)
+    int32_t pad;
     SegInfo seg[kMaxSeg];
     const int32_t *sb_inst;   // per surface block: internal instance
     const int32_t *sb_chunk;  // per surface block: chunk of 64 elements
@@ -451,13 +453,14 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, const in
 // x = 64 (w % nw) + lane of row group w / nw, with nw = pitch / 64
 // wavefronts per row and 4 / nw row groups (with nw = 3 the fourth
 // wavefront idles but keeps the barriers).  A row group owns R consecutive
-// rows and a chunk of up to kZChunk planes.  It marches through the planes:
-// for plane p it advances step t on its rows plus one halo row on each side
-// (of those only the population moving into the owned rows is kept) and
-// holds the post-collision values in registers; then it finishes step t + 1
-// on plane p - 1, whose seven incoming populations are now all known: the
-// +x / -x ones shifted across lanes (across wavefronts through LDS), +y / -y
-// from the neighbouring rows, +z / -z from planes p - 2 and p.  Per two
+// rows and a chunk of up to zchunk planes (chosen per handle: kZChunk, or
+// less when so few blocks would leave the chip idle).  It marches through
+// the planes: for plane p it advances step t on its rows plus one halo row
+// on each side (of those only the population moving into the owned rows is
+// kept) and holds the post-collision values in registers; then it finishes
+// step t + 1 on plane p - 1, whose seven incoming populations are now all
+// known: the +x / -x ones shifted across lanes (across wavefronts through
+// LDS), +y / -y from the neighbouring rows, +z / -z from planes p - 2 and p.  Per two
 // steps each plane is read about (R + 2) / R times (the halo rows, and the
 // halo planes at the chunk ends, are read twice) and written once, against
 // two reads and two writes for two one-step launches.
@@ -502,7 +505,7 @@ __device__ inline C c2_at(gptr<const C> c2box, int crow, int bb_lo0, int bb_n0, 
     return c0sq;
 }
 
-template <typename S, int R, int NT>
+template <typename S, int R, int NT, bool PF>
 __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const int bsrc, int lb,
                                       typename StoreTraits<S>::C (*xe)[4][R][2])
 {
@@ -523,15 +526,15 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
     const int nx = sg.nx, ny = sg.ny, nz = sg.nz;
     const int pitch = I.pitch;
     const int64_t plane = I.plane;
-    const int nw = pitch / 64;
-    const int ng = 4 / nw;
+    const int nw = pitch / 64;  // wavefronts per row
+    const int ng = 4 / nw;      // row groups per block
     const int lane = threadIdx.x & 63;
     const int w = wave_uniform(threadIdx.x >> 6);
     const int g = w / nw, xs = w - g * nw;
     const bool active = g < ng;
     const int y0 = (yb * ng + (active ? g : 0)) * R;
-    const int z0 = zc * kZChunk;
-    const int zlen = min(kZChunk, nz - z0);
+    const int z0 = zc * a.zchunk;
+    const int zlen = min(a.zchunk, nz - z0);
     const int x = xs * 64 + lane;
     const bool xin = active && x < nx;
     const C c0sq = (C)I.c0sq;
@@ -558,31 +561,61 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
 #pragma unroll
     for (int j = 0; j < R; ++j) Q0[j] = Qpx[j] = Qmx[j] = Qpy[j] = Qmy[j] = Qpz[j] = Qpz2[j] = C(0);
 
+    // the seven pulled populations (step t) of row y0 + j of plane zq; the
+    // +x / -x neighbours by loads offset by one element
+    auto load_row = [&](int zq, int j, E *f) {
+        const int zm = (zq == 0) ? nz - 1 : zq - 1;
+        const int zn = (zq == nz - 1) ? 0 : zq + 1;
+        int y = y0 + j;
+        y = (y < 0) ? y + ny : (y >= ny ? y - ny : y);
+        const int ym = (y == 0) ? ny - 1 : y - 1;
+        const int yn = (y == ny - 1) ? 0 : y + 1;
+        if (xin) {
+            const int64_t row = ((int64_t)zq * ny + y) * pitch;
+            f[0] = *at(src + row, ux);
+            f[1] = *at(src + plane + row - 1, ux);
+            f[2] = *at(src + 2 * plane + row + 1, ux);
+            f[3] = *at(src + 3 * plane + ((int64_t)zq * ny + ym) * pitch, ux);
+            f[4] = *at(src + 4 * plane + ((int64_t)zq * ny + yn) * pitch, ux);
+            f[5] = *at(src + 5 * plane + ((int64_t)zm * ny + y) * pitch, ux);
+            f[6] = *at(src + 6 * plane + ((int64_t)zn * ny + y) * pitch, ux);
+        }
+    };
+    auto load_plane = [&](int zq, E (&L)[R + 2][7]) {
+#pragma unroll
+        for (int j = -1; j <= R; ++j) load_row(zq, j, L[j + 1]);
+    };
+    auto wrapz = [&](int z) { return (z < 0) ? z + nz : (z >= nz ? z - nz : z); };
+
+    // PF: the loads of plane p + 1 are in flight while plane p is computed
+    E Lnext[R + 2][7];
+    if (PF) load_plane(wrapz(z0 - 1), Lnext);
+
     for (int p = -1; p <= zlen; ++p) {
-        int zp = z0 + p;
-        zp = (zp < 0) ? zp + nz : (zp >= nz ? zp - nz : zp);
-        const int zm = (zp == 0) ? nz - 1 : zp - 1;
-        const int zn = (zp == nz - 1) ? 0 : zp + 1;
+        const int zp = wrapz(z0 + p);
         const bool own_plane = p >= 0 && p < zlen;
         const int sl = (p + 2) & 1;
+        E Lcur[R + 2][7];
+        if (PF) {
+#pragma unroll
+            for (int j = 0; j < R + 2; ++j)
+#pragma unroll
+                for (int i = 0; i < 7; ++i) Lcur[j][i] = Lnext[j][i];
+            if (p < zlen) load_plane(wrapz(z0 + p + 1), Lnext);
+        }
         C N0[R], Npx[R], Nmx[R], Npy[R], Nmy[R], Npz[R], Nmz[R];
         C prev_py = C(0);
 #pragma unroll
         for (int j = -1; j <= R; ++j) {
             int y = y0 + j;
             y = (y < 0) ? y + ny : (y >= ny ? y - ny : y);
-            const int ym = (y == 0) ? ny - 1 : y - 1;
-            const int yn = (y == ny - 1) ? 0 : y + 1;
+            E Lrow[7];
+            if constexpr (!PF) load_row(zp, j, Lrow);
+            const E *L = PF ? Lcur[j + 1] : Lrow;
             C f[7], o[7];
             if (xin) {
-                const int64_t row = ((int64_t)zp * ny + y) * pitch;
-                f[0] = T::to_c(*at(src + row, ux));
-                f[1] = T::to_c(*at(src + plane + row - 1, ux));
-                f[2] = T::to_c(*at(src + 2 * plane + row + 1, ux));
-                f[3] = T::to_c(*at(src + 3 * plane + ((int64_t)zp * ny + ym) * pitch, ux));
-                f[4] = T::to_c(*at(src + 4 * plane + ((int64_t)zp * ny + yn) * pitch, ux));
-                f[5] = T::to_c(*at(src + 5 * plane + ((int64_t)zm * ny + y) * pitch, ux));
-                f[6] = T::to_c(*at(src + 6 * plane + ((int64_t)zn * ny + y) * pitch, ux));
+#pragma unroll
+                for (int i = 0; i < 7; ++i) f[i] = T::to_c(L[i]);
                 if (x == 0) f[1] = C(0);       // nothing enters from outside the sheets
                 if (x == nx - 1) f[2] = C(0);
                 C rho = f[0];
@@ -817,8 +850,8 @@ __device__ inline int xcd_block(int b, int n)
     return (x < r) ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
 }
 
-template <typename S, int R, int NT>
-__global__ void __launch_bounds__(kStepThreads) step2_kernel(StepArgs a)
+template <typename S, int R, int NT, bool PF>
+__global__ void __launch_bounds__(kStepThreads, PF ? 3 : 4) step2_kernel(StepArgs a)
 {
     using C = typename StoreTraits<S>::C;
     __shared__ double lds[4][64][4];
@@ -827,7 +860,8 @@ __global__ void __launch_bounds__(kStepThreads) step2_kernel(StepArgs a)
     const int b = blockIdx.x;
     // the long lattice blocks first, the short measurement blocks fill the tail
     if (b < a.ntask) {
-        lattice2_block<S, R, NT>(a, t, ((int)a.tp[1] + a.dt) % kNumBuf, xcd_block(b, a.ntask), xe);
+        lattice2_block<S, R, NT, PF>(a, t, ((int)a.tp[1] + a.dt) % kNumBuf, xcd_block(b, a.ntask),
+                                     xe);
         return;
     }
     measure_part<3, C>(a, t, b - a.ntask, lds);

@@ -420,6 +420,7 @@ struct lb_wave {
     int n = 0, dim = 0, storage = 0, vx = 1, xm = 0, nt = 0;
     int fused = 1;                    // lattice steps per launch (1 or 2)
     bool fused_ok = false;            // every instance fits the two-step kernel
+    int zchunk = kZChunk;             // planes per chunk of the two-step kernel
     std::vector<int> blk0;            // internal order, size n + 1: two-step blocks
     char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -539,14 +540,21 @@ void launch(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
 
 // Rows per row group of the two-step kernel (FP64 holds twice the registers).
 int two_step_rows(int storage) { return storage == LB_F64 ? 2 : 4; }
+// Two-step plane chunks shrink (down to kMinZChunk) until a handle has this
+// many blocks: 256 CUs hold 1024 of them at four wavefronts per SIMD.
+constexpr int64_t kMinBlocks2 = 1024;
+constexpr int kMinZChunk = 4;
 
+// Prefetching the next plane's loads pays where the registers allow it
+// (4- and 2-byte storage: three wavefronts per SIMD); FP64 loads in place.
 template <typename S, int R>
 void launch2_t(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
 {
+    constexpr bool PF = sizeof(typename StoreTraits<S>::R) <= 4;
     if (h->nt == 0)
-        hipLaunchKernelGGL((step2_kernel<S, R, 0>), dim3(blocks), dim3(kStepThreads), 0, st, a);
+        hipLaunchKernelGGL((step2_kernel<S, R, 0, PF>), dim3(blocks), dim3(kStepThreads), 0, st, a);
     else
-        hipLaunchKernelGGL((step2_kernel<S, R, 1>), dim3(blocks), dim3(kStepThreads), 0, st, a);
+        hipLaunchKernelGGL((step2_kernel<S, R, 1, PF>), dim3(blocks), dim3(kStepThreads), 0, st, a);
 }
 
 void launch2(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
@@ -601,6 +609,7 @@ void emit_step(const lb_wave *h, StepArgs a, int64_t t, int32_t dt, int nst, hip
     auto first_of = [&](const SegInfo &sg) { return two ? sg.blk0 : sg.task0; };
     const int n_active = two ? h->blk0[na] : h->task0[na];
     a.dt = dt;
+    a.zchunk = h->zchunk;
     size_t s = 0;
     bool first = true;
     do {
@@ -967,22 +976,33 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
         blob_off.push_back(L.off_sbtab);
     }
     // two-step decomposition: row groups of R rows, 4 / nw groups per block,
-    // chunks of kZChunk planes
+    // chunks of zchunk planes: the longest chunk (fewest re-read halo planes)
+    // that still gives the chip about kMinBlocks2 blocks
     {
         const int R = two_step_rows(h->storage);
-        h->fused_ok = (h->dim == 3);
-        h->blk0.assign(n_inst + 1, 0);
-        for (int ii = 0; ii < n_inst; ++ii) {
-            const InstDev &I = h->hinst[ii];
-            int bpi = 0;
-            if (I.xbc == 0 && I.pitch <= kTwoStepMaxPitch) {
-                const int ng = 4 / (I.pitch / 64);
-                if (I.ny % (R * ng) == 0)
-                    bpi = (I.ny / (R * ng)) * ((I.nz + kZChunk - 1) / kZChunk);
+        auto blocks_for = [&](int zc, std::vector<int> *b0) {
+            bool ok = (h->dim == 3);
+            if (b0) b0->assign(n_inst + 1, 0);
+            int64_t total = 0;
+            for (int ii = 0; ii < n_inst; ++ii) {
+                const InstDev &I = h->hinst[ii];
+                int bpi = 0;
+                if (I.xbc == 0 && I.pitch <= kTwoStepMaxPitch) {
+                    const int ng = 4 / (I.pitch / 64);
+                    if (I.ny % (R * ng) == 0) bpi = (I.ny / (R * ng)) * ((I.nz + zc - 1) / zc);
+                }
+                if (bpi == 0) ok = false;
+                total += bpi;
+                if (b0) (*b0)[ii + 1] = (*b0)[ii] + bpi;
             }
-            if (bpi == 0) h->fused_ok = false;
-            h->blk0[ii + 1] = h->blk0[ii] + bpi;
-        }
+            return ok ? total : (int64_t)-1;
+        };
+        h->zchunk = kZChunk;
+        while (h->zchunk > kMinZChunk && blocks_for(h->zchunk, nullptr) >= 0 &&
+               blocks_for(h->zchunk, nullptr) < kMinBlocks2)
+            h->zchunk /= 2;
+        h->fused_ok = blocks_for(h->zchunk, &h->blk0) >= 0 &&
+                      h->blk0[n_inst] < std::numeric_limits<int32_t>::max() / 2;
         if (!h->fused_ok) std::fill(h->blk0.begin(), h->blk0.end(), 0);
     }
     // segments: maximal runs of equal shape in internal order

@@ -38,8 +38,9 @@ def rel(a, b):
     return float(np.abs(np.asarray(a) - np.asarray(b)).max() / max(np.abs(b).max(), 1e-300))
 
 
-def gpu_run(P, p, n, storage, init=None, vx=1, trace=True):
+def gpu_run(P, p, n, storage, init=None, vx=1, trace=True, spl=1):
     h = P.LBWave([p], storage=storage, trace_steps=n if trace else 0)
+    h.set_steps_per_launch(spl)
     if isinstance(vx, tuple):
         h.set_variant(*vx)
     else:
@@ -265,13 +266,16 @@ def test_autotune_keeps_results(P):
     h = P.LBWave([p], storage="f32")
     ms = h.autotune(4)
     assert ms > 0 and h.tile() in (1, 2, 4) and h.t == 0
-    say(f"  chosen variant {h.variant()} at {ms:.4f} ms/step")
+    say(f"  chosen variant {h.variant()}, {h.steps_per_launch()} steps per launch, "
+        f"at {ms:.4f} ms/step")
     h.step(20)
     a = h.get_state(0)
-    h.set_variant(1, 0, 0)
-    h.reset()
-    h.step(20)
-    assert np.array_equal(a, h.get_state(0))
+    for spl in (1, 2):
+        h.set_steps_per_launch(spl)
+        h.set_variant(1, 0, 0)
+        h.reset()
+        h.step(20)
+        assert np.array_equal(a, h.get_state(0))
     h.close()
 
 
@@ -312,17 +316,18 @@ def test_cavity_calibration_parity(P, orc, nx, c0, lam):
 
 def test_full_size_sphere_fields(P, orc):
     # The 3D workload's lattice (256 x 128 x 128, FP32) in the launch
-    # configuration the benchmark times: a few steps from a seeded random
-    # state compared over every cell, plus the force at each step.
+    # configuration the benchmark times (two steps per launch): a few steps
+    # from a seeded random state compared over every cell, plus the force at
+    # each step.
     cal_x, k = 126.63, 2 * np.pi / 256
     p = workloads.sphere_3d(cal_x, k, math.pi / 4)
     p["avg_start"] = 0
     ncell = 256 * 128 * 128
     init = workloads.random_state(77, ncell, 7, scale=0.05)
-    n = 3
-    say("full-size sphere fields fp32, 3 steps")
+    n = 4
+    say("full-size sphere fields fp32, 4 steps, two per launch")
     ref = orc.run(p, n, fnew_init=init, want_fields=True, want_trace=True)
-    got = gpu_run(P, p, n, "f32", init=init)
+    got = gpu_run(P, p, n, "f32", init=init, spl=2)
     ef = rel(got["fnew"], ref["fnew"])
     et = rel(got["F_trace"], ref["F_trace"])
     say(f"  field {ef:.3e} trace {et:.3e}")

@@ -49,8 +49,9 @@ def say(*a):
     print(*a, flush=True)
 
 
-def run(P, p, storage):
+def run(P, p, storage, spl=1):
     h = P.LBWave([p], storage=storage)
+    h.set_steps_per_launch(spl)
     h.step(p["n_steps"])
     F, nacc = h.force()
     h.close()
@@ -68,7 +69,7 @@ def test_full_size_sphere_against_oracle_goldens(P, storage):
     for j, rec in sorted(g["positions"].items()):
         p = workloads.sphere_3d(g["x_mid"], g["k"], rec["kh"])
         np.testing.assert_allclose(p["center"], rec["center"], atol=1e-12)
-        F = run(P, p, storage)
+        F = run(P, p, storage, spl=2)  # two steps per launch, as the benchmark runs it
         e = abs(F[0] - rec["F_avg"][0]) / abs(rec["F_avg"][0])
         say(f"kh_{j} {storage}: F_x {F[0]:.8e} oracle {rec['F_avg'][0]:.8e} rel {e:.2e}")
         assert e <= BOUND["full"][storage]
@@ -101,7 +102,8 @@ def test_cylinder_all_storages(P, orc):
 
 
 def test_sixteen_positions_batched(P):
-    # The benchmark's configuration: all 16 positions in one handle, FP32.
+    # The benchmark's configuration: all 16 positions in one handle, FP32,
+    # two steps per launch, graph replay of 64-step chunks.
     # Checks the golden positions and the shape the paper reports
     # (sin 2kh: largest near kh = pi/4, vanishing at the node kh = pi/2).
     if not os.path.exists(GOLD):
@@ -110,6 +112,7 @@ def test_sixteen_positions_batched(P):
     khs = workloads.sphere_3d_positions(16)
     probs = [workloads.sphere_3d(g["x_mid"], g["k"], kh) for kh in khs]
     h = P.LBWave(probs, storage="f32")
+    h.set_steps_per_launch(2)
     h.set_graph(64)
     h.step(probs[0]["n_steps"])
     F, nacc = h.force()

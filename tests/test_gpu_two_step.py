@@ -131,3 +131,4 @@ def test_two_step_rejected_where_it_does_not_apply(P):
     with pytest.raises(P.LBError):
         h.set_steps_per_launch(2)
     h.close()
+
