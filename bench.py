@@ -50,13 +50,16 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip training and timing the force surrogate")
     ap.add_argument("--surrogate-batch", type=int, default=1 << 20)
+    ap.add_argument("--surrogate-steps", type=int, default=8000,
+                    help="Adam steps of the surrogate's training (0: time the untrained network)")
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--variant", default=None,
                     help="kernel variant 'cells_per_lane,x_mode,nontemporal[,steps_per_launch]' "
                          "(skips autotune)")
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "batch"],
+    ap.add_argument("--workload", default="sphere", choices=["sphere", "batch", "surrogate"],
                     help="sphere: the 16-position 3D sphere (default); batch: the seeded uneven "
-                         "batch of boxes (forces/s batched vs plain)")
+                         "batch of boxes (forces/s batched vs plain); surrogate: the force "
+                         "network alone (training, held-out error, inference rate)")
     ap.add_argument("--batch-seed", type=int, default=2404)
     ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--graph", type=int, default=64,
@@ -140,7 +143,7 @@ def cpu_baseline(x_mid, k, n_steps):
                       f"256x128x128 lattice with surface measurement ({dt:.1f} s)"}
 
 
-def surrogate_leg(stream, batch):
+def surrogate_leg(stream, batch, steps=8000):
     """Train the surrogate on the LB data, score it held out, time its fused inference."""
     import torch
     from paper_2404_02346_amd import surrogate as S
@@ -149,7 +152,10 @@ def surrogate_leg(stream, batch):
     if not all(os.path.exists(f) for f in files + [test]):
         return None
     train_sets = [json.load(open(f)) for f in files]
-    net, log, train_s = S.fit(train_sets)
+    if steps > 0:
+        net, log, train_s = S.fit(train_sets, steps=steps)
+    else:  # untrained network: the inference kernel's speed does not depend on the weights
+        net, log, train_s = S.MLP(max_batch=1024, seed=0), [(0, float("nan"))], 0.0
     te = S.table(json.load(open(test)))
     err = S.error_metric(net.predict(S.normalize(*te[:4])), te[4])
     x = torch.rand(batch, S.N_IN, device="cuda") * 2 - 1
@@ -248,6 +254,12 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         batch_workload(args)
+        return
+    if args.workload == "surrogate":
+        import torch
+        torch.cuda.set_device(0)
+        sur = surrogate_leg(torch.cuda.current_stream(), args.surrogate_batch, args.surrogate_steps)
+        print(json.dumps({"mode": "surrogate", **(sur or {})}), flush=True)
         return
     import torch
     import paper_2404_02346_amd as P
@@ -427,7 +439,7 @@ def main():
         out["forces_x"] = [float(v) for v in F[:, 0]]
         out["n_accum"] = int(nacc[0])
     if not args.no_surrogate:
-        sur = surrogate_leg(stream, args.surrogate_batch)
+        sur = surrogate_leg(stream, args.surrogate_batch, args.surrogate_steps)
         if sur is not None:
             out["forces_per_s"]["surrogate"] = sur["forces_per_s"]
             out["surrogate"] = sur
