@@ -67,8 +67,9 @@ int lb_mlp_forward(lb_mlp *h, const float *dev_x, int32_t B, float *dev_y);
 
 /* The training forward (one MFMA GEMM launch per layer, activations kept in
  * the workspace for the backward pass) for B <= max_batch samples; same
- * arguments as lb_mlp_forward.  Its output agrees with lb_mlp_forward up to
- * the FP32 summation order.  Asynchronous. */
+ * arguments as lb_mlp_forward.  Both run the same MFMA sequence per output
+ * (sums starting at the bias, K in the same 32-wide steps) and the same
+ * roundings, so their outputs agree bit for bit.  Asynchronous. */
 int lb_mlp_forward_layered(lb_mlp *h, const float *dev_x, int32_t B, float *dev_y);
 
 /* Gradient of the mean squared error L = (1/B) sum (y - t)^2 with respect to
@@ -87,6 +88,15 @@ int lb_mlp_last_loss(lb_mlp *h, double *loss);
  * bits; D 16 x 16 row-major FP32), computed by the same fragment mapping as
  * the network's products: a check of the matrix-core lane layout. */
 int lb_mlp_mfma_probe(const uint16_t *dev_A, const uint16_t *dev_B, float *dev_D,
+                      void *hip_stream);
+
+/* The network's activation applied elementwise: out = g(z) = z Phi(z), the
+ * exact (erf) GELU, or with derivative != 0 its derivative g'(z) = Phi(z) +
+ * z phi(z), in the FP32 form every layer uses (Phi from Hastings' rational-
+ * exponential erf, within 3e-7 of the exact value).  dev_z and dev_out hold n
+ * FP32 values (0 <= n <= 2^40; they may alias).  Asynchronous on hip_stream.
+ * LB_EINVAL for a negative or too large n or a NULL pointer with n > 0. */
+int lb_mlp_activation(const float *dev_z, int64_t n, int32_t derivative, float *dev_out,
                       void *hip_stream);
 
 #ifdef __cplusplus

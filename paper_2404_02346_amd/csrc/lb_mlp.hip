@@ -38,20 +38,57 @@ constexpr int param_offset_b(int l) { return param_offset_w(l) + kDims[l + 1] * 
 constexpr int kParams = param_offset_w(kLayers);
 
 __device__ inline float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__host__ __device__ inline uint16_t f2bf(float f)
+// FP32 -> BF16, round to nearest even (one hardware conversion on gfx950)
+__device__ inline uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+// two at once: a in the low half, b in the high half.  The pair is converted as
+// one vector and split by the caller with shifts: reading a single element of a
+// BF16 vector is lowered wrongly by this compiler (element 1 reads element 0).
+__device__ inline uint32_t to_bf16x2(float a, float b)
 {
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest, ties to even
-    return (uint16_t)(u >> 16);
+    typedef float f32x2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2{a, b}), bf16x2));
 }
 
-// exact GELU and its derivative
-__device__ inline float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// Standard normal distribution in the tail, h = Phi(-|z|) = (1 - erf(|z| / sqrt 2)) / 2,
+// from Hastings' rational-exponential form of erf (Abramowitz & Stegun 7.1.26,
+// |error| <= 1.5e-7): for x >= 0, 1 - erf(x) ~ t (a1 + t (a2 + t (a3 + t (a4 + t a5))))
+// exp(-x^2), t = 1 / (1 + p x).  Here x = |z| / sqrt 2, with 1/sqrt 2 folded into p and
+// the factor 1/2 into the a_i.  In FP32 h is within 3e-7 of Phi(-|z|); e = exp(-z^2 / 2)
+// is returned for the derivative.  About a dozen instructions against some 35 for the
+// library erf, which evaluates both of its branches.
+__device__ inline float normal_tail(float z, float &e)
+{
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.23164188826636f, fabsf(z), 1.0f));
+    float q = fmaf(t, 0.5307027145f, -0.7265760135f);
+    q = fmaf(t, q, 0.7107068705f);
+    q = fmaf(t, q, -0.142248368f);
+    q = fmaf(t, q, 0.127414796f);
+    e = __builtin_amdgcn_exp2f(z * (z * -0.72134752044448f));  // exp(-z^2 / 2)
+    return (q * t) * e;
+}
+
+// max(z, 0) as one instruction (the compiler's fmaxf first quiets a possible
+// signalling NaN with a second one; a NaN z still gives a NaN GELU below)
+__device__ inline float relu(float z)
+{
+    float r;
+    asm("v_max_f32 %0, 0, %1" : "=v"(r) : "v"(z));
+    return r;
+}
+
+// exact GELU g(z) = z Phi(z) = max(z, 0) - |z| Phi(-|z|), and its derivative
+// g'(z) = Phi(z) + z phi(z)
+__device__ inline float gelu(float z)
+{
+    float e;
+    return fmaf(-fabsf(z), normal_tail(z, e), relu(z));
+}
 __device__ inline float gelu_d(float z)
 {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) +
-           z * 0.39894228040143268f * expf(-0.5f * z * z);
+    float e;
+    const float h = normal_tail(z, e);
+    return fmaf(z * 0.39894228040143268f, e, z >= 0.0f ? 1.0f - h : h);
 }
 
 enum Epi { EPI_BIAS_GELU = 0, EPI_BIAS = 1, EPI_STORE = 2, EPI_GELU_BWD = 3 };
@@ -81,11 +118,17 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
     const int m_blk = blockIdx.y * TM, n_blk = blockIdx.x * TN;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
+    // with a bias the sums start from it, as in the fused inference kernel, so that
+    // both forwards round every activation identically
+    const bool has_bias = g.epi == EPI_BIAS_GELU || g.epi == EPI_BIAS;
     f32x4 acc[2][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+        const int n = n_blk + wn * 32 + j * 16 + (lane & 15);
+        const float b0 = (has_bias && n < g.N) ? g.bias[n] : 0.f;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < 2; ++i) acc[i][j] = f32x4{b0, b0, b0, b0};
+    }
 
     for (int k0 = 0; k0 < g.K; k0 += TK) {
 #pragma unroll
@@ -129,18 +172,16 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
                 const float c = acc[i][j][v];
                 const int64_t o = (int64_t)m * g.ldo + n;
                 switch (g.epi) {
-                case EPI_BIAS_GELU: {
-                    const float z = c + g.bias[n];
-                    g.outf[o] = z;
-                    g.outb[o] = f2bf(gelu(z));
+                case EPI_BIAS_GELU:
+                    g.outf[o] = c;
+                    g.outb[o] = to_bf16(gelu(c));
                     break;
-                }
-                case EPI_BIAS: g.outf[o] = c + g.bias[n]; break;
+                case EPI_BIAS: g.outf[o] = c; break;
                 case EPI_STORE: g.outf[o] = c; break;
                 default: {
                     const float d = c * gelu_d(g.zprev[o]);
                     g.outf[o] = d;
-                    g.outb[o] = f2bf(d);
+                    g.outb[o] = to_bf16(d);
                 }
                 }
             }
@@ -149,7 +190,7 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 __global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = f2bf(x[i]);
+    if (i < n) y[i] = to_bf16(x[i]);
 }
 
 // delta = 2 (y - t) / B (FP32 and BF16), loss = sum (y - t)^2 / B in FP64 (one block)
@@ -162,7 +203,7 @@ __global__ void __launch_bounds__(256) loss_kernel(const float *y, const float *
         const float e = y[b] - t[b];
         const float d = 2.0f * e / (float)B;
         df[b] = d;
-        db[b] = f2bf(d);
+        db[b] = to_bf16(d);
         s += (double)e * (double)e;
     }
     red[threadIdx.x] = s;
@@ -218,19 +259,25 @@ __global__ void adam_kernel(float *p, const float *g, float *m, float *v, uint16
     v[i] = vi;
     const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
     p[i] = pi;
-    pb[i] = f2bf(pi);
+    pb[i] = to_bf16(pi);
 }
 
 __global__ void mirror_kernel(const float *p, uint16_t *pb, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) pb[i] = f2bf(p[i]);
+    if (i < n) pb[i] = to_bf16(p[i]);
 }
 
 __global__ void zero_f32_kernel(float *p, int64_t n)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0.f;
+}
+
+__global__ void activation_kernel(const float *z, int64_t n, int derivative, float *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = derivative ? gelu_d(z[i]) : gelu(z[i]);
 }
 
 // one MFMA tile with the network's fragment mapping (lane-layout check)
@@ -254,13 +301,16 @@ __global__ void __launch_bounds__(64) mfma_probe_kernel(const uint16_t *A, const
 
 // Fused inference: one block carries kInferRows samples through all layers,
 // their activations staying in LDS (BF16, rows padded by 8 elements so that
-// the 16-byte fragment reads of 16 consecutive rows hit distinct banks).
-// Hidden layers run on MFMA with the same operand roundings as the training
-// forward: BF16 weights and activations, FP32 accumulation, FP32 bias, GELU
-// in FP32 rounded to BF16.  Each of the four wavefronts owns 64 output
-// columns for all kInferRows rows; its weight fragments come from global
-// memory (every block reads the same 128 KiB per layer, so they are L2 hits)
-// one K step ahead of use.
+// the 16-byte fragment reads of 16 consecutive rows spread over the banks).
+// Every layer runs on MFMA with the same operand roundings as the training
+// forward: BF16 weights and activations, FP32 accumulation and bias, GELU in
+// FP32 rounded to BF16.  The first layer's K = 4 is one 32-wide MFMA step with
+// the other 28 k zero, and the last layer's single output is column 0 of a
+// 16-column tile whose other columns have zero weights.  In the first four
+// layers each of the four wavefronts owns 64 output columns for all
+// kInferRows rows and its accumulators start at the bias; the weight fragments
+// come from global memory (every block reads the same 128 KiB per layer, so
+// they are L2 hits) one K step ahead of use.
 constexpr int kInferRows = 128;
 constexpr int kActLd = kHidden + 8;
 
@@ -269,41 +319,75 @@ __global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__
                                                     const uint16_t *__restrict__ pb,
                                                     float *__restrict__ y)
 {
+    constexpr int RT = kInferRows / 16;  // row tiles
     __shared__ __attribute__((aligned(16))) uint16_t act[kInferRows][kActLd];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int kl = 8 * (lane >> 4);  // this lane's k offset within a 32-wide step
     const int64_t row0 = (int64_t)blockIdx.x * kInferRows;
+    f32x4 acc[RT][4];
 
-    // layer 0 (K = kIn): FP32 sums of exact BF16 products, in k order, then the bias
+    auto start = [&](int l) {
+        const float *bias = p + param_offset_b(l);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const float bn = bias[w * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+            for (int i = 0; i < RT; ++i) acc[i][j] = f32x4{bn, bn, bn, bn};
+        }
+    };
+    // GELU of the accumulators, rounded to BF16 in pairs, into this wavefront's columns
+    auto finish = [&]() {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = w * 64 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < RT; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; v += 2) {
+                    const uint32_t g = to_bf16x2(gelu(acc[i][j][v]), gelu(acc[i][j][v + 1]));
+                    const int r = i * 16 + 4 * (lane >> 4) + v;
+                    act[r][col] = (uint16_t)g;
+                    act[r + 1][col] = (uint16_t)(g >> 16);
+                }
+        }
+    };
+
+    // layer 0 (K = kIn): lanes 0..15 carry k = 0..3 of their row (A) or column (B)
     {
         const uint16_t *W = pb + param_offset_w(0);
-        const float *bias = p + param_offset_b(0);
-        const int n = tid;  // one output column per thread
-        float wn[kIn];
+        start(0);
+        bf16x8 bfr[4];
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) wn[k] = bf2f(W[n * kIn + k]);
-        const float bn = bias[n];
-        for (int r = 0; r < kInferRows; ++r) {
-            const int64_t gr = row0 + r;
-            float z = 0.f;
-            if (gr < B) {
+        for (int j = 0; j < 4; ++j) {
+            s16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+            if (lane < 16) {
+                const int col = w * 64 + j * 16 + lane;
 #pragma unroll
-                for (int k = 0; k < kIn; ++k) z += bf2f(f2bf(x[gr * kIn + k])) * wn[k];
+                for (int k = 0; k < kIn; ++k) b[k] = (short)W[col * kIn + k];
             }
-            act[r][n] = f2bf(gelu(z + bn));
+            bfr[j] = __builtin_bit_cast(bf16x8, b);
         }
+#pragma unroll
+        for (int i = 0; i < RT; ++i) {
+            s16x8 a = {0, 0, 0, 0, 0, 0, 0, 0};
+            const int64_t r = row0 + i * 16 + lane;
+            if (lane < 16 && r < B) {
+#pragma unroll
+                for (int k = 0; k < kIn; ++k) a[k] = (short)to_bf16(x[r * kIn + k]);
+            }
+            const bf16x8 af = __builtin_bit_cast(bf16x8, a);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[j], acc[i][j], 0, 0, 0);
+        }
+        finish();
+        __syncthreads();
     }
-    __syncthreads();
 
-    // hidden layers 1 .. kLayers-2 (256 x 256) on MFMA
+    // hidden layers 1 .. kLayers-2 (256 x 256)
     for (int l = 1; l < kLayers - 1; ++l) {
         const uint16_t *W = pb + param_offset_w(l);  // W[n][k], k fastest
-        const float *bias = p + param_offset_b(l);
-        f32x4 acc[kInferRows / 16][4];
-#pragma unroll
-        for (int i = 0; i < kInferRows / 16; ++i)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const int kl = 8 * (lane >> 4);
+        start(l);
         s16x8 bnext[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -322,7 +406,7 @@ __global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__
                 }
             }
 #pragma unroll
-            for (int i = 0; i < kInferRows / 16; ++i) {
+            for (int i = 0; i < RT; ++i) {
                 const bf16x8 af = __builtin_bit_cast(
                     bf16x8, *reinterpret_cast<const s16x8 *>(&act[i * 16 + (lane & 15)][k0 + kl]));
 #pragma unroll
@@ -331,36 +415,40 @@ __global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__
             }
         }
         __syncthreads();  // every wavefront has read this layer's input
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = w * 64 + j * 16 + (lane & 15);
-            const float bn = bias[col];
-#pragma unroll
-            for (int i = 0; i < kInferRows / 16; ++i)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    act[i * 16 + 4 * (lane >> 4) + v][col] = f2bf(gelu(acc[i][j][v] + bn));
-        }
+        finish();
         __syncthreads();
     }
 
-    // output layer (256 -> 1): two threads per row, FP32 sums of exact BF16 products
+    // output layer (256 -> 1): wavefront w takes row tiles 2w and 2w + 1; the B
+    // fragment is nonzero only in column 0 (lanes 0, 16, 32, 48)
     {
         const uint16_t *W = pb + param_offset_w(kLayers - 1);
         const float bias = p[param_offset_b(kLayers - 1)];
-        const int r = tid >> 1, half = tid & 1;
-        float s = 0.f;
-#pragma unroll 4
-        for (int c = 0; c < kHidden / 2; c += 8) {
-            const int k = half * (kHidden / 2) + c;
-            const s16x8 a = *reinterpret_cast<const s16x8 *>(&act[r][k]);
-            const s16x8 b = *reinterpret_cast<const s16x8 *>(W + k);
+        f32x4 o[RT / 4];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) s += bf2f((uint16_t)a[e]) * bf2f((uint16_t)b[e]);
+        for (int ii = 0; ii < RT / 4; ++ii) o[ii] = f32x4{bias, bias, bias, bias};
+#pragma unroll
+        for (int k0 = 0; k0 < kHidden; k0 += 32) {
+            s16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
+            if ((lane & 15) == 0) b = *reinterpret_cast<const s16x8 *>(W + k0 + kl);
+            const bf16x8 bf = __builtin_bit_cast(bf16x8, b);
+#pragma unroll
+            for (int ii = 0; ii < RT / 4; ++ii) {
+                const int rt = (RT / 4) * w + ii;
+                const bf16x8 af = __builtin_bit_cast(
+                    bf16x8, *reinterpret_cast<const s16x8 *>(&act[rt * 16 + (lane & 15)][k0 + kl]));
+                o[ii] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, o[ii], 0, 0, 0);
+            }
         }
-        s += __shfl_xor(s, 1);
-        const int64_t gr = row0 + r;
-        if (half == 0 && gr < B) y[gr] = s + bias;
+        if ((lane & 15) == 0) {
+#pragma unroll
+            for (int ii = 0; ii < RT / 4; ++ii)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t r = row0 + ((RT / 4) * w + ii) * 16 + 4 * (lane >> 4) + v;
+                    if (r < B) y[r] = o[ii][v];
+                }
+        }
     }
 }
 
@@ -681,6 +769,20 @@ int lb_mlp_mfma_probe(const uint16_t *dev_A, const uint16_t *dev_B, float *dev_D
     if (!dev_A || !dev_B || !dev_D) return lbw_fail_msg(LB_EINVAL, "NULL argument");
     hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, static_cast<hipStream_t>(hip_stream),
                        dev_A, dev_B, dev_D);
+    MLP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+int lb_mlp_activation(const float *dev_z, int64_t n, int32_t derivative, float *dev_out,
+                      void *hip_stream)
+{
+    if (n < 0 || (n > 0 && (!dev_z || !dev_out)))
+        return lbw_fail_msg(LB_EINVAL, "activation: bad arguments");
+    if (n > ((int64_t)1 << 40)) return lbw_fail_msg(LB_EINVAL, "activation: n too large");
+    if (n == 0) return LB_OK;
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(activation_kernel, dim3((unsigned)blocks), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), dev_z, n, derivative ? 1 : 0, dev_out);
     MLP_TRY(hipGetLastError());
     return LB_OK;
 }

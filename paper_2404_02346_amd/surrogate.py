@@ -54,6 +54,7 @@ def _mlp_lib():
                                         C.c_float]
         L.lb_mlp_last_loss.argtypes = [vp, C.POINTER(C.c_double)]
         L.lb_mlp_mfma_probe.argtypes = [vp, vp, vp, vp]
+        L.lb_mlp_activation.argtypes = [vp, C.c_int64, C.c_int32, vp, vp]
         L._mlp_ready = True
     return L
 
@@ -221,6 +222,18 @@ def mfma_probe(A_bits: np.ndarray, B_bits: np.ndarray) -> np.ndarray:
                                                C.c_void_p(d.data_ptr()),
                                                C.c_void_p(s.cuda_stream)))
     return d.cpu().numpy().reshape(16, 16)
+
+
+def activation(z: np.ndarray, derivative: bool = False) -> np.ndarray:
+    """The network's GELU (or its derivative) as the library computes it, in FP32."""
+    import torch
+    zt = torch.as_tensor(np.ascontiguousarray(z, dtype=np.float32).ravel(), device="cuda")
+    out = torch.empty_like(zt)
+    s = torch.cuda.current_stream()
+    lbwave._check(_mlp_lib().lb_mlp_activation(C.c_void_p(zt.data_ptr()), zt.numel(),
+                                               int(bool(derivative)), C.c_void_p(out.data_ptr()),
+                                               C.c_void_p(s.cuda_stream)))
+    return out.cpu().numpy().reshape(np.shape(z))
 
 
 # ---------------------------------------------------------------------------

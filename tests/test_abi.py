@@ -185,3 +185,8 @@ def test_mlp_sizes_and_argument_errors(P):
     assert lib.lb_mlp_forward(None, None, 1, None) == -1
     assert lib.lb_mlp_forward_layered(None, None, 1, None) == -1
     assert lib.lb_mlp_destroy(None) == 0
+    lib.lb_mlp_activation.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.lb_mlp_activation(None, -1, 0, None, None) == -1
+    assert lib.lb_mlp_activation(None, 5, 0, None, None) == -1
+    assert lib.lb_mlp_activation(None, 0, 1, None, None) == 0  # nothing to do, no device call
