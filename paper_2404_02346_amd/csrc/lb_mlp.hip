@@ -307,30 +307,36 @@ __global__ void __launch_bounds__(64) mfma_probe_kernel(const uint16_t *A, const
 // FP32 rounded to BF16.  The first layer's K = 4 is one 32-wide MFMA step with
 // the other 28 k zero, and the last layer's single output is column 0 of a
 // 16-column tile whose other columns have zero weights.  In the first four
-// layers each of the four wavefronts owns 64 output columns for all
-// kInferRows rows and its accumulators start at the bias; the weight fragments
-// come from global memory (every block reads the same 128 KiB per layer, so
-// they are L2 hits) one K step ahead of use.
+// layers each of the kInferWaves wavefronts owns 256 / kInferWaves output
+// columns for all kInferRows rows and its accumulators start at the bias; the
+// weight fragments come from global memory (every block reads the same
+// 128 KiB per layer, so they are L2 hits) one K step ahead of use.  The LDS
+// tile (67.6 KB) allows two blocks per CU.
 constexpr int kInferRows = 128;
+constexpr int kInferWaves = 8;
+constexpr int kInferThreads = 64 * kInferWaves;
 constexpr int kActLd = kHidden + 8;
 
-__global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__ x, int B,
-                                                    const float *__restrict__ p,
-                                                    const uint16_t *__restrict__ pb,
-                                                    float *__restrict__ y)
+__global__ void __launch_bounds__(kInferThreads, kInferWaves / 2)
+    infer_kernel(const float *__restrict__ x, int B, const float *__restrict__ p,
+                 const uint16_t *__restrict__ pb, float *__restrict__ y)
 {
-    constexpr int RT = kInferRows / 16;  // row tiles
+    constexpr int RT = kInferRows / 16;        // row tiles
+    constexpr int CW = kHidden / kInferWaves;  // columns per wavefront
+    constexpr int JT = CW / 16;                // column tiles per wavefront
+    constexpr int OT = RT / kInferWaves;       // output-layer row tiles per wavefront
+    static_assert(JT >= 1 && OT >= 1, "wavefront count");
     __shared__ __attribute__((aligned(16))) uint16_t act[kInferRows][kActLd];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int kl = 8 * (lane >> 4);  // this lane's k offset within a 32-wide step
     const int64_t row0 = (int64_t)blockIdx.x * kInferRows;
-    f32x4 acc[RT][4];
+    f32x4 acc[RT][JT];
 
     auto start = [&](int l) {
         const float *bias = p + param_offset_b(l);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float bn = bias[w * 64 + j * 16 + (lane & 15)];
+        for (int j = 0; j < JT; ++j) {
+            const float bn = bias[w * CW + j * 16 + (lane & 15)];
 #pragma unroll
             for (int i = 0; i < RT; ++i) acc[i][j] = f32x4{bn, bn, bn, bn};
         }
@@ -338,8 +344,8 @@ __global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__
     // GELU of the accumulators, rounded to BF16 in pairs, into this wavefront's columns
     auto finish = [&]() {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = w * 64 + j * 16 + (lane & 15);
+        for (int j = 0; j < JT; ++j) {
+            const int col = w * CW + j * 16 + (lane & 15);
 #pragma unroll
             for (int i = 0; i < RT; ++i)
 #pragma unroll
@@ -356,12 +362,12 @@ __global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__
     {
         const uint16_t *W = pb + param_offset_w(0);
         start(0);
-        bf16x8 bfr[4];
+        bf16x8 bfr[JT];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < JT; ++j) {
             s16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
             if (lane < 16) {
-                const int col = w * 64 + j * 16 + lane;
+                const int col = w * CW + j * 16 + lane;
 #pragma unroll
                 for (int k = 0; k < kIn; ++k) b[k] = (short)W[col * kIn + k];
             }
@@ -377,7 +383,7 @@ __global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__
             }
             const bf16x8 af = __builtin_bit_cast(bf16x8, a);
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < JT; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[j], acc[i][j], 0, 0, 0);
         }
         finish();
@@ -388,20 +394,20 @@ __global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__
     for (int l = 1; l < kLayers - 1; ++l) {
         const uint16_t *W = pb + param_offset_w(l);  // W[n][k], k fastest
         start(l);
-        s16x8 bnext[4];
+        s16x8 bnext[JT];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = w * 64 + j * 16 + (lane & 15);
+        for (int j = 0; j < JT; ++j) {
+            const int col = w * CW + j * 16 + (lane & 15);
             bnext[j] = *reinterpret_cast<const s16x8 *>(W + col * kHidden + kl);
         }
         for (int k0 = 0; k0 < kHidden; k0 += 32) {
-            bf16x8 bfr[4];
+            bf16x8 bfr[JT];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) bfr[j] = __builtin_bit_cast(bf16x8, bnext[j]);
+            for (int j = 0; j < JT; ++j) bfr[j] = __builtin_bit_cast(bf16x8, bnext[j]);
             if (k0 + 32 < kHidden) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int col = w * 64 + j * 16 + (lane & 15);
+                for (int j = 0; j < JT; ++j) {
+                    const int col = w * CW + j * 16 + (lane & 15);
                     bnext[j] = *reinterpret_cast<const s16x8 *>(W + col * kHidden + k0 + 32 + kl);
                 }
             }
@@ -410,7 +416,7 @@ __global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__
                 const bf16x8 af = __builtin_bit_cast(
                     bf16x8, *reinterpret_cast<const s16x8 *>(&act[i * 16 + (lane & 15)][k0 + kl]));
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
+                for (int j = 0; j < JT; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[j], acc[i][j], 0, 0, 0);
             }
         }
@@ -419,22 +425,22 @@ __global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__
         __syncthreads();
     }
 
-    // output layer (256 -> 1): wavefront w takes row tiles 2w and 2w + 1; the B
+    // output layer (256 -> 1): wavefront w takes row tiles OT w .. OT w + OT - 1; the B
     // fragment is nonzero only in column 0 (lanes 0, 16, 32, 48)
     {
         const uint16_t *W = pb + param_offset_w(kLayers - 1);
         const float bias = p[param_offset_b(kLayers - 1)];
-        f32x4 o[RT / 4];
+        f32x4 o[OT];
 #pragma unroll
-        for (int ii = 0; ii < RT / 4; ++ii) o[ii] = f32x4{bias, bias, bias, bias};
+        for (int ii = 0; ii < OT; ++ii) o[ii] = f32x4{bias, bias, bias, bias};
 #pragma unroll
         for (int k0 = 0; k0 < kHidden; k0 += 32) {
             s16x8 b = {0, 0, 0, 0, 0, 0, 0, 0};
             if ((lane & 15) == 0) b = *reinterpret_cast<const s16x8 *>(W + k0 + kl);
             const bf16x8 bf = __builtin_bit_cast(bf16x8, b);
 #pragma unroll
-            for (int ii = 0; ii < RT / 4; ++ii) {
-                const int rt = (RT / 4) * w + ii;
+            for (int ii = 0; ii < OT; ++ii) {
+                const int rt = OT * w + ii;
                 const bf16x8 af = __builtin_bit_cast(
                     bf16x8, *reinterpret_cast<const s16x8 *>(&act[rt * 16 + (lane & 15)][k0 + kl]));
                 o[ii] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, o[ii], 0, 0, 0);
@@ -442,10 +448,10 @@ __global__ void __launch_bounds__(256, 2) infer_kernel(const float *__restrict__
         }
         if ((lane & 15) == 0) {
 #pragma unroll
-            for (int ii = 0; ii < RT / 4; ++ii)
+            for (int ii = 0; ii < OT; ++ii)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int64_t r = row0 + ((RT / 4) * w + ii) * 16 + 4 * (lane >> 4) + v;
+                    const int64_t r = row0 + (OT * w + ii) * 16 + 4 * (lane >> 4) + v;
                     if (r < B) y[r] = o[ii][v];
                 }
         }
@@ -701,7 +707,7 @@ int lb_mlp_forward(lb_mlp *h, const float *dev_x, int32_t B, float *dev_y)
     if (B < 1) return lbw_fail_msg(LB_EINVAL, "batch must be >= 1");
     if (!dev_x || !dev_y) return lbw_fail_msg(LB_EINVAL, "NULL argument");
     const unsigned blocks = (unsigned)(((int64_t)B + kInferRows - 1) / kInferRows);
-    hipLaunchKernelGGL(infer_kernel, dim3(blocks), dim3(256), 0, h->stream, dev_x, B,
+    hipLaunchKernelGGL(infer_kernel, dim3(blocks), dim3(kInferThreads), 0, h->stream, dev_x, B,
                        h->at<float>(h->L.p), h->at<uint16_t>(h->L.pb), dev_y);
     MLP_TRY(hipGetLastError());
     return LB_OK;
