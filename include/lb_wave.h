@@ -57,6 +57,15 @@ typedef enum { LB_F64 = 0, LB_F32 = 1, LB_F16 = 2, LB_BF16 = 3 } lb_storage;
 /* Boundary along x: the paper's driven sheets, or periodic (no sheets). */
 typedef enum { LB_XBC_DRIVEN = 0, LB_XBC_PERIODIC = 1 } lb_xbc;
 
+/* Where the wave comes from.  LB_SRC_SHEET: the driven sheet x = 1 (none in
+ * periodic mode).  LB_SRC_POINT: one node, the oscillating point source of
+ * the paper's first validation (Sec. "Lattice-Boltzmann for acoustics",
+ * eq. waves_with_pointSource): after every collision the node src_cell
+ * takes f^eq(rho_a sin(omega t), J1) with J1 its own pre-collision momentum,
+ * the rule of the source sheet (eq. imposingfields).  A point source needs
+ * periodic x (no sheets) and keeps one lattice step per launch. */
+typedef enum { LB_SRC_SHEET = 0, LB_SRC_POINT = 1 } lb_source;
+
 typedef enum {
     LB_OK = 0,
     LB_EINVAL = -1,      /* bad argument, shape or parameter */
@@ -81,7 +90,7 @@ typedef struct lb_wave_desc {
     double obj_radius;          /* R_p */
     double obj_cp;              /* sound speed inside the object c_p */
     double obj_d;               /* "square thickness" d of the tanh profile (paper: 4) */
-    double rho_a;               /* source amplitude: rho1(x = 1) = rho_a sin(omega t) */
+    double rho_a;               /* source amplitude: rho1 = rho_a sin(omega t) on the source */
     double omega;               /* drive angular frequency (rad/step) */
     double wall_phi;            /* bounce-back damping Phi in [0, 1) (paper: 0.99) */
     int32_t n_surf;             /* number of surface elements N (may be 0) */
@@ -91,6 +100,8 @@ typedef struct lb_wave_desc {
     int64_t avg_start;          /* F(t) enters the average for t >= avg_start */
     int64_t max_steps;          /* the instance freezes after this many steps; <= 0: never */
     int64_t trace_steps;        /* keep F(t) for t < trace_steps (0: no trace) */
+    int32_t src_kind;           /* lb_source (0, the sheet, for descriptors set to zero) */
+    int32_t src_cell[3];        /* LB_SRC_POINT: the source node (x, y, z); z = 0 in 2D */
 } lb_wave_desc;
 
 typedef struct lb_wave lb_wave;  /* opaque handle */
@@ -98,7 +109,8 @@ typedef struct lb_wave lb_wave;  /* opaque handle */
 /* Check descriptors on the host only (no device call).  Returns LB_OK or the
  * first error: LB_EINVAL (shapes, dim, storage mismatch between instances,
  * missing surface arrays, rho0 <= 0, wall_phi outside [0, 1), nx < 3 with
- * driven x), LB_EUNSTABLE (c0, c_p or any c_field value above 1/sqrt(dim),
+ * driven x, a point source with driven x or a source node outside the
+ * lattice), LB_EUNSTABLE (c0, c_p or any c_field value above 1/sqrt(dim),
  * the stability bound of the tau = 1/2 scheme), LB_EGEOMETRY (a 3-point
  * stencil reaches x < 2 or x > nx-2 in driven mode, where the sheets change
  * the moments, or leaves 0 <= x < nx in periodic mode). */

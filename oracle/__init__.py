@@ -46,6 +46,7 @@ class _Desc(C.Structure):
         ("n_surf", C.c_int32),
         ("surf_xyz", _dp), ("surf_normal", _dp), ("surf_area", _dp),
         ("avg_start", C.c_int64),
+        ("src_kind", C.c_int32), ("src_cell", C.c_int32 * 3),
     ]
 
 
@@ -71,7 +72,7 @@ def _load():
         lib.orc_interp.restype = C.c_int
         lib.orc_surface_integral.argtypes = [C.POINTER(_Desc), _dp, _dp, _dp]
         lib.orc_run.argtypes = [C.POINTER(_Desc), C.c_int64, _dp, _dp, _dp, _dp, _i64p, _dp,
-                                C.c_int64, C.c_int64]
+                                C.c_int64, C.c_int64, _i64p, C.c_int64, _dp]
         lib.orc_run.restype = C.c_int
         _lib = lib
     return _lib
@@ -125,6 +126,10 @@ class _Bound:
         d.surf_normal = _ptr(self.surf_normal)
         d.surf_area = _ptr(self.surf_area)
         d.avg_start = int(p.get("avg_start", 0))
+        sc = p.get("src_cell")  # a point source at this node (periodic x)
+        d.src_kind = 0 if sc is None else 1
+        for a in range(3):
+            d.src_cell[a] = 0 if sc is None else int((list(sc) + [0, 0, 0])[a])
         self.desc = d
         self.Q = 2 * dim + 1
         self.ncell = d.nx * d.ny * d.nz
@@ -224,13 +229,15 @@ def surface_integral(p: dict, rhoI, JI) -> np.ndarray:
 # ---------------------------------------------------------------------------
 
 def run(p: dict, n_steps: int, fnew_init=None, want_fields: bool = False,
-        want_trace: bool = False, line: tuple[int, int] | None = None) -> dict:
+        want_trace: bool = False, line: tuple[int, int] | None = None,
+        probes=None) -> dict:
     """Run the method for ``n_steps`` steps (see ``orc_run`` in lb_oracle.c).
 
     Returns a dict with ``F_avg`` (3,), ``n_acc``, and on request ``fnew``
     (the post-collision state of the last step, shape cells x Q, cell index
     (z*ny + y)*nx + x), ``F_trace`` (n_steps, 3) and ``rho_line``
-    (line_n, nx) for steps line_t0 .. line_t0+line_n-1.
+    (line_n, nx) for steps line_t0 .. line_t0+line_n-1; with ``probes`` (cell
+    indices) also ``rho_probe`` (line_n, len(probes)) for the same steps.
     """
     lib = _load()
     b = _Bound(p)
@@ -247,8 +254,15 @@ def run(p: dict, n_steps: int, fnew_init=None, want_fields: bool = False,
     if line is not None:
         lt0, ln = int(line[0]), int(line[1])
         rl = np.zeros(ln * b.desc.nx)
+    pr = rp = None
+    if probes is not None:
+        assert line is not None, "probes are recorded over the line window"
+        pr = np.ascontiguousarray(np.asarray(probes, dtype=np.int64).reshape(-1))
+        rp = np.zeros(ln * pr.size)
     st = lib.orc_run(C.byref(b.desc), int(n_steps), _ptr(init), _ptr(fout), _ptr(trace),
-                     _ptr(Favg), C.byref(nacc), _ptr(rl), lt0, ln)
+                     _ptr(Favg), C.byref(nacc), _ptr(rl), lt0, ln,
+                     None if pr is None else pr.ctypes.data_as(_i64p), 0 if pr is None else pr.size,
+                     _ptr(rp))
     if st != 0:
         raise ValueError(f"oracle run failed with status {st}")
     out = {"F_avg": Favg, "n_acc": nacc.value}
@@ -258,6 +272,8 @@ def run(p: dict, n_steps: int, fnew_init=None, want_fields: bool = False,
         out["F_trace"] = trace.reshape(int(n_steps), 3)
     if line is not None:
         out["rho_line"] = rl.reshape(ln, b.desc.nx)
+    if pr is not None:
+        out["rho_probe"] = rp.reshape(ln, pr.size)
     return out
 
 

@@ -18,6 +18,8 @@
  *   - BGK collision with tau = 1/2                           (eq. LBM-Collision)
  *   - damped bounce-back walls at x = 0 and x = Lx-1         (eq. bounce-back)
  *   - imposed density rho_a sin(omega t) at x = 1            (eq. imposingfields)
+ *   - or, in periodic mode, at one node: the oscillating     (eq. waves_with_pointSource,
+ *     point source of the first validation                    imposed like the sheet)
  *   - advection f_i(x + v_i) = f_i^new(x)                    (eq. LBM-Advection)
  *   - per-cell sound speed of the object                     (eq. sound_speed_object,
  *                                                             sign read so that c = c_p inside)
@@ -63,6 +65,8 @@ typedef struct orc_desc {
     const double *surf_normal;/* n_surf*3 unit normals */
     const double *surf_area;  /* n_surf element sizes dS_k */
     int64_t avg_start;        /* accumulate F(t) for t >= avg_start */
+    int32_t src_kind;         /* 0: the sheet x = 1 (driven mode); 1: the node src_cell */
+    int32_t src_cell[3];      /* point-source node (periodic mode only) */
 } orc_desc;
 
 /* Velocity set: rest vector plus the 2*dim unit vectors (Sec. LBW, Fig. velocity_sets). */
@@ -269,18 +273,20 @@ static void build_c2(const orc_desc *D, double *c2)
  *      driven mode the wall planes x = 0 and x = nx-1 take the damped
  *      bounce-back of the pre-collision populations (eq. bounce-back) and
  *      the source plane x = 1 takes f^eq(rho_a sin(omega t), J1(1, y, z))
- *      (eq. imposingfields);
+ *      (eq. imposingfields); in periodic mode with src_kind = 1 the single
+ *      node src_cell takes f^eq(rho_a sin(omega t), J1) in the same way;
  * and then
  *   4. interpolates rho1, J1 of f(t) onto the surface and evaluates F(t)
  *      (eq. arf_integral_LBM); for t >= avg_start adds F(t) to the FP64
  *      accumulator.
  * Outputs (each optional): fnew_out = f^new of the last step, F_trace
  * (n_steps*3), F_avg (3) and n_acc, rho_line (rho1 along x at y = z = 0 for
- * steps line_t0 .. line_t0+line_n-1, line_n*nx values).
+ * steps line_t0 .. line_t0+line_n-1, line_n*nx values), rho_probe (rho1 at
+ * the n_probe cell indices probe[] for the same steps, line_n*n_probe values).
  */
 int orc_run(const orc_desc *D, int64_t n_steps, const double *fnew_init, double *fnew_out,
             double *F_trace, double *F_avg, int64_t *n_acc, double *rho_line, int64_t line_t0,
-            int64_t line_n)
+            int64_t line_n, const int64_t *probe, int64_t n_probe, double *rho_probe)
 {
     const int dim = D->dim, Q = 2 * dim + 1;
     if (dim != 2 && dim != 3) return ORC_EINVAL;
@@ -288,6 +294,13 @@ int orc_run(const orc_desc *D, int64_t n_steps, const double *fnew_init, double 
     if (D->xbc == ORC_XBC_DRIVEN && D->nx < 3) return ORC_EINVAL;
     const int64_t ncell = (int64_t)D->nx * D->ny * D->nz;
     const int driven = (D->xbc == ORC_XBC_DRIVEN);
+    const int point = (D->src_kind == 1);
+    if (D->src_kind != 0 && D->src_kind != 1) return ORC_EINVAL;
+    if (point && (driven || D->src_cell[0] < 0 || D->src_cell[0] >= D->nx || D->src_cell[1] < 0 ||
+                  D->src_cell[1] >= D->ny || D->src_cell[2] < 0 || D->src_cell[2] >= D->nz))
+        return ORC_EINVAL;
+    for (int64_t j = 0; j < n_probe; ++j)
+        if (probe[j] < 0 || probe[j] >= ncell) return ORC_EINVAL;
 
     double *prev = (double *)calloc((size_t)(ncell * Q), sizeof(double));
     double *next = (double *)malloc(sizeof(double) * (size_t)(ncell * Q));
@@ -335,7 +348,9 @@ int orc_run(const orc_desc *D, int64_t n_steps, const double *fnew_init, double 
                     double *out = next + c * Q;
                     if (driven && (x == 0 || x == D->nx - 1)) {
                         for (int i = 0; i < Q; ++i) out[i] = D->wall_phi * f[OPP[i]];
-                    } else if (driven && x == 1) {
+                    } else if ((driven && x == 1) ||
+                               (point && x == D->src_cell[0] && y == D->src_cell[1] &&
+                                z == D->src_cell[2])) {
                         orc_feq(dim, c2[c], rho_src, J + 3 * c, out);
                     } else {
                         orc_collide_cell(dim, c2[c], f, out);
@@ -344,6 +359,8 @@ int orc_run(const orc_desc *D, int64_t n_steps, const double *fnew_init, double 
 
         if (rho_line && t >= line_t0 && t < line_t0 + line_n)
             for (int x = 0; x < D->nx; ++x) rho_line[(t - line_t0) * D->nx + x] = rho[x];
+        if (rho_probe && t >= line_t0 && t < line_t0 + line_n)
+            for (int64_t j = 0; j < n_probe; ++j) rho_probe[(t - line_t0) * n_probe + j] = rho[probe[j]];
 
         /* 4. interpolation and surface integral */
         if (D->n_surf > 0) {

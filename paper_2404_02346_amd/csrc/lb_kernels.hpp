@@ -157,6 +157,8 @@ struct InstDev {
     double src_amp;          // rho_a times the storage scale
     double omega, wall_phi;
     int64_t max_steps;       // frozen for t >= max_steps
+    int32_t src_pt[3];       // point-source node (when src_point)
+    int32_t src_point;       // 1: the node src_pt is imposed after every step
     // measurement
     int32_t mb_lo[3];        // moment box origin (cells whose rho, J the surface reads)
     int32_t mb_n[3];         // moment box extent (0 -> no measurement)
@@ -236,6 +238,22 @@ __device__ inline int wave_uniform(int v) { return __builtin_amdgcn_readfirstlan
 //   f^new_0    = 2 (1 - dim c^2) rho - f_0,
 // with c = c(x) the local sound speed.
 // ---------------------------------------------------------------------------
+// imposed density rs with the cell's own momentum (eq. imposingfields):
+// f^eq(rs, J) of the pre-collision populations f
+template <int DIM, typename C>
+__device__ inline void impose_rule(const C *f, C c2, C rs, C *out)
+{
+    constexpr int Q = 2 * DIM + 1;
+    const C h = (C)0.5;
+    out[0] = rs * ((C)1 - (C)DIM * c2);
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+        const C Ja = f[i] - f[i + 1];
+        out[i] = h * (c2 * rs + Ja);
+        out[i + 1] = h * (c2 * rs - Ja);
+    }
+}
+
 template <int DIM, typename C>
 __device__ inline void cell_rule(const C *f, C rho, C c2, int x, int nx, bool driven, C phi, C rs,
                                  C *out)
@@ -250,15 +268,7 @@ __device__ inline void cell_rule(const C *f, C rho, C c2, int x, int nx, bool dr
             out[i + 1] = phi * f[i];
         }
     } else if (driven && x == 1) {
-        // imposed density with the cell's own momentum (eq. imposingfields)
-        const C h = (C)0.5;
-        out[0] = rs * ((C)1 - (C)DIM * c2);
-#pragma unroll
-        for (int i = 1; i < Q; i += 2) {
-            const C Ja = f[i] - f[i + 1];
-            out[i] = h * (c2 * rs + Ja);
-            out[i + 1] = h * (c2 * rs - Ja);
-        }
+        impose_rule<DIM, C>(f, c2, rs, out);
     } else {
         const C c2rho = c2 * rho;
         out[0] = (C)2 * ((C)1 - (C)DIM * c2) * rho - f[0];
@@ -869,6 +879,56 @@ __global__ void __launch_bounds__(kStepThreads, PF ? 3 : 4) step2_kernel(StepArg
 
 // Device step counter: set, or advance after a replayed sequence.
 // The counter holds {t, t mod 3} (the phase saves the kernels a 64-bit division).
+// Point source (the paper's oscillating point source): after the lattice
+// step t, the source node of every instance that has one takes
+// f^eq(rho_a sin(omega t), J1) from its own pre-collision populations, as the
+// source sheet does; x, y and z are periodic.  One thread per instance, in
+// stream order after the step's lattice launch and before the next one.
+template <int DIM, typename S>
+__global__ void point_source_kernel(const InstDev *inst, int n_inst, const int64_t *tp, int32_t dt)
+{
+    using T = StoreTraits<S>;
+    using R = typename T::R;
+    using C = typename T::C;
+    constexpr int Q = 2 * DIM + 1;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_inst) return;
+    const InstDev &I = inst[k];
+    const int64_t t = tp[0] + dt;
+    if (!I.src_point || (I.max_steps > 0 && t >= I.max_steps)) return;
+    const int bsrc = ((int)tp[1] + dt) % kNumBuf;
+    const R *src = static_cast<const R *>(I.buf[bsrc]);
+    R *dst = static_cast<R *>(I.buf[bsrc == kNumBuf - 1 ? 0 : bsrc + 1]);
+    const int x = I.src_pt[0], y = I.src_pt[1], z = I.src_pt[2];
+    auto at = [&](int i, int xx, int yy, int zz) {
+        xx = xx < 0 ? xx + I.nx : (xx >= I.nx ? xx - I.nx : xx);
+        yy = yy < 0 ? yy + I.ny : (yy >= I.ny ? yy - I.ny : yy);
+        zz = zz < 0 ? zz + I.nz : (zz >= I.nz ? zz - I.nz : zz);
+        return (int64_t)i * I.plane + ((int64_t)zz * I.ny + yy) * I.pitch + xx;
+    };
+    // the pulled populations f_i(x) = f^new_i(x - v_i) of the previous step
+    C f[Q];
+    f[0] = T::to_c(src[at(0, x, y, z)]);
+    f[1] = T::to_c(src[at(1, x - 1, y, z)]);
+    f[2] = T::to_c(src[at(2, x + 1, y, z)]);
+    f[3] = T::to_c(src[at(3, x, y - 1, z)]);
+    f[4] = T::to_c(src[at(4, x, y + 1, z)]);
+    if (DIM == 3) {
+        f[5] = T::to_c(src[at(5, x, y, z - 1)]);
+        f[6] = T::to_c(src[at(6, x, y, z + 1)]);
+    }
+    C c2 = (C)I.c0sq;
+    const int bx = x - I.bb_lo[0], by = y - I.bb_lo[1], bz = (DIM == 3) ? z - I.bb_lo[2] : 0;
+    if (I.bb_n[0] > 0 && bx >= 0 && bx < I.bb_n[0] && by >= 0 && by < I.bb_n[1] &&
+        (DIM == 2 || (bz >= 0 && bz < I.bb_n[2])))
+        c2 = static_cast<const C *>(I.c2box)[((int64_t)bz * I.bb_n[1] + by) * I.bb_n[0] + bx];
+    const C rs = (C)(I.src_amp * sin(I.omega * (double)t));
+    C out[Q];
+    impose_rule<DIM, C>(f, c2, rs, out);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) dst[at(i, x, y, z)] = T::to_r(out[i]);
+}
+
 __global__ void set_step_kernel(int64_t *tp, int64_t v)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {

@@ -237,6 +237,16 @@ int check_one(const lb_wave_desc &d, const lb_wave_desc &d0, int idx)
         return fail(LB_EINVAL, "instance %d: rho_a and omega must be finite", idx);
     if (d.avg_start < 0 || d.trace_steps < 0)
         return fail(LB_EINVAL, "instance %d: avg_start and trace_steps must be >= 0", idx);
+    if (d.src_kind != LB_SRC_SHEET && d.src_kind != LB_SRC_POINT)
+        return fail(LB_EINVAL, "instance %d: bad src_kind", idx);
+    if (d.src_kind == LB_SRC_POINT) {
+        if (d.xbc != LB_XBC_PERIODIC)
+            return fail(LB_EINVAL, "instance %d: a point source needs periodic x", idx);
+        const int32_t *s = d.src_cell;
+        if (s[0] < 0 || s[0] >= d.nx || s[1] < 0 || s[1] >= d.ny || s[2] < 0 || s[2] >= d.nz)
+            return fail(LB_EINVAL, "instance %d: source node (%d, %d, %d) outside the lattice",
+                        idx, s[0], s[1], s[2]);
+    }
     // sizes: rows and wave tasks are indexed with 32-bit integers
     const long pitch = (long)align_up((size_t)d.nx, 64);
     const long rows = (long)d.ny * d.nz;
@@ -439,6 +449,7 @@ struct lb_wave {
     int32_t *d_sb_chunk = nullptr;
     std::vector<int> sb_first;        // internal order, size n + 1
     bool any_surf = false;
+    bool any_point = false;           // some instance has a point source
     int64_t t = 0;                    // lattice steps done
     int64_t meas = 0;                 // steps whose chunk partials exist
     int64_t red = 0;                  // steps reduced into the accumulators
@@ -538,6 +549,27 @@ void launch(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
     }
 }
 
+// The point sources of step t (the lattice launches of step t come first in
+// stream order); two-step launches never run on a handle with point sources.
+template <int DIM, typename S>
+void launch_point_s(const lb_wave *h, const StepArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((point_source_kernel<DIM, S>), dim3((h->n + 63) / 64), dim3(64), 0, st,
+                       a.inst, h->n, a.tp, a.dt);
+}
+void launch_point(const lb_wave *h, const StepArgs &a, hipStream_t st)
+{
+    const bool d2 = h->dim == 2;
+    switch (h->storage) {
+    case LB_F64: d2 ? launch_point_s<2, double>(h, a, st) : launch_point_s<3, double>(h, a, st); break;
+    case LB_F32: d2 ? launch_point_s<2, float>(h, a, st) : launch_point_s<3, float>(h, a, st); break;
+    case LB_F16:
+        d2 ? launch_point_s<2, _Float16>(h, a, st) : launch_point_s<3, _Float16>(h, a, st);
+        break;
+    default: d2 ? launch_point_s<2, bf16>(h, a, st) : launch_point_s<3, bf16>(h, a, st); break;
+    }
+}
+
 // Rows per row group of the two-step kernel (FP64 holds twice the registers).
 int two_step_rows(int storage) { return storage == LB_F64 ? 2 : 4; }
 // Two-step plane chunks shrink (down to kMinZChunk) until a handle has this
@@ -633,6 +665,7 @@ void emit_step(const lb_wave *h, StepArgs a, int64_t t, int32_t dt, int nst, hip
         first = false;
         s += k;
     } while (s < h->segs.size() && first_of(h->segs[s]) < n_active);
+    if (h->any_point && !two) launch_point(h, a, st);
 }
 
 // Make the device counter equal `t` in stream order if dt would not fit.
@@ -901,6 +934,9 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
         I.omega = d.omega;
         I.wall_phi = d.wall_phi;
         I.max_steps = d.max_steps;
+        I.src_point = d.src_kind == LB_SRC_POINT ? 1 : 0;
+        for (int a = 0; a < 3; ++a) I.src_pt[a] = I.src_point ? d.src_cell[a] : 0;
+        if (I.src_point) h->any_point = true;
         for (int a = 0; a < 3; ++a) {
             I.mb_lo[a] = P.mbox.lo[a];
             I.mb_n[a] = P.mbox.n[a];
@@ -1001,8 +1037,10 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
         while (h->zchunk > kMinZChunk && blocks_for(h->zchunk, nullptr) >= 0 &&
                blocks_for(h->zchunk, nullptr) < kMinBlocks2)
             h->zchunk /= 2;
-        h->fused_ok = blocks_for(h->zchunk, &h->blk0) >= 0 &&
-                      h->blk0[n_inst] < std::numeric_limits<int32_t>::max() / 2;
+        // (blocks_for also sizes blk0, which the segments below read in every case)
+        const bool fits = blocks_for(h->zchunk, &h->blk0) >= 0 &&
+                          h->blk0[n_inst] < std::numeric_limits<int32_t>::max() / 2;
+        h->fused_ok = fits && !h->any_point;
         if (!h->fused_ok) std::fill(h->blk0.begin(), h->blk0.end(), 0);
     }
     // segments: maximal runs of equal shape in internal order

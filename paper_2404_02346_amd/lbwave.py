@@ -40,6 +40,7 @@ class Desc(C.Structure):
         ("n_surf", C.c_int32),
         ("surf_xyz", _dp), ("surf_normal", _dp), ("surf_area", _dp),
         ("avg_start", C.c_int64), ("max_steps", C.c_int64), ("trace_steps", C.c_int64),
+        ("src_kind", C.c_int32), ("src_cell", C.c_int32 * 3),
     ]
 
 
@@ -153,6 +154,10 @@ def make_descs(problems, storage: str = "f32", freeze_at_n_steps: bool = False,
             ms = p.get("n_steps", 0)
         d.max_steps = int(ms or 0)
         d.trace_steps = int(p.get("trace_steps", trace_steps))
+        sc = p.get("src_cell")  # a point source at this node (periodic x)
+        d.src_kind = 0 if sc is None else 1
+        for a in range(3):
+            d.src_cell[a] = 0 if sc is None else int((list(sc) + [0, 0, 0])[a])
     return arr, keep
 
 

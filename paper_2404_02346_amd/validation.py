@@ -1,8 +1,22 @@
 """Validation cases of the wave model beyond the radiation force (Sec. "Lattice-
-Boltzmann for acoustics"): a plane interface between two media.
+Boltzmann for acoustics"): an oscillating point source and a plane interface
+between two media.
 
-The paper models the interface as a smooth change of the sound speed along x
-(eq. c_plane_int),
+Point source (eq. waves_with_pointSource and the Green's-function solution
+after it).  One node of a periodic cube is imposed, like the source sheet,
+with rho1 = rho_a sin(w t) and its own momentum.  Far from it the field is
+the outgoing spherical wave of the inhomogeneous wave equation,
+rho1 = A sin(w t - k r + phi) / r: the complex amplitude P(r) at the drive
+frequency has |P| r constant and phase -k r, with k the lattice wavenumber
+along the ray (1 - cos w = c^2 sum_a (1 - cos k_a) for the wave vector k n).
+The printed prefactor of the solution is not dimensionally consistent, and a
+node-sized source has no continuum strength, so A and phi are fitted, not
+predicted.  The record ends before the first image from the periodic copies
+arrives and starts one period after the direct wave has passed the
+outermost fitted node.
+
+Plane interface.  The paper models the interface as a smooth change of the
+sound speed along x (eq. c_plane_int),
     c(x) = ((c_p - c_0)/2) tanh((x - x_i)/w) + (c_p + c_0)/2,
 with c_0 = 0.5 and c_p = 0.25, and checks that pressure and normal velocity
 are continuous across it, p_I + p_R = p_T and u_I + u_R = u_T, to 1%.
@@ -29,6 +43,105 @@ import math
 import numpy as np
 
 from . import lbwave
+
+
+def point_source_problem(n: int = 64, lam: float = 12.0, c0: float = 0.5, rho_a: float = 1.0,
+                         dim: int = 3):
+    """A periodic cube (square in 2D) of n cells per side with the source node at its centre."""
+    s = n // 2
+    p = {"dim": dim, "nx": n, "ny": n, "xbc": "periodic", "c0": c0, "rho0": 1.0,
+         "center": (0.0, 0.0, 0.0), "radius": 0.0, "cp": c0, "rho_a": rho_a,
+         "omega": 2.0 * math.pi * c0 / lam, "wall_phi": 0.99, "avg_start": 0, "lam": lam,
+         "src_cell": (s, s, s if dim == 3 else 0)}
+    if dim == 3:
+        p["nz"] = n
+    return p
+
+
+def ray_cells(p: dict, direction, r_max: float):
+    """Nodes s + m d (m = 1, 2, ...) along a lattice direction d within r_max: distances, cell indices."""
+    d = np.asarray(list(direction) + [0] * (3 - len(direction)), dtype=np.int64)
+    s = np.asarray(p["src_cell"], dtype=np.int64)
+    nx, ny = p["nx"], p["ny"]
+    step = float(np.linalg.norm(d))
+    m = np.arange(1, int(r_max / step) + 1)
+    xyz = s[None, :] + m[:, None] * d[None, :]
+    return m * step, (xyz[:, 2] * ny + xyz[:, 1]) * nx + xyz[:, 0]
+
+
+def ray_wavenumber(omega: float, c: float, direction) -> float:
+    """|k| of the lattice plane wave of frequency omega whose wave vector points along direction."""
+    d = np.asarray(direction, dtype=np.float64)
+    u = d / np.linalg.norm(d)
+    lo, hi = 0.0, math.pi
+    for _ in range(200):  # 1 - cos w = c^2 sum_a (1 - cos(k u_a)) is increasing in k on [0, pi]
+        mid = 0.5 * (lo + hi)
+        if c * c * float(np.sum(1.0 - np.cos(mid * u))) < 1.0 - math.cos(omega):
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def point_source_window(p: dict, r_fit: float):
+    """(t0, n): one drive period that starts a period after the direct wave has passed r_fit and
+    ends before the first image (distance n - r from the nearest periodic copy) reaches r_fit."""
+    c0, n = p["c0"], p["nx"]
+    period = int(round(2 * math.pi / p["omega"]))
+    t_end = int((n - r_fit) / c0) - 4
+    t0 = t_end - period
+    assert t0 >= r_fit / c0 + period, "the box is too small for this r_fit"
+    return t0, period
+
+
+def spherical_amplitude(p: dict, rho_tr: np.ndarray, t0: int):
+    """Complex amplitude P = (2/T) sum_t rho1(t) exp(-i w t) over one period, per column."""
+    n = rho_tr.shape[0]
+    t = t0 + np.arange(n)
+    return (2.0 / n) * (rho_tr * np.exp(-1j * p["omega"] * t)[:, None]).sum(axis=0)
+
+
+def rho_probe_gpu(p: dict, cells, t0: int, n: int, storage: str = "f64") -> np.ndarray:
+    """rho1 of steps t0 .. t0+n-1 at the given cells (GPU library), read from the workspace."""
+    import torch
+    cells = np.asarray(cells, dtype=np.int64)
+    h = lbwave.LBWave([p], storage=storage)
+    v = h.state_view(0)
+    dt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16,
+          "bf16": torch.bfloat16}[storage]
+    nx, ny = p["nx"], p["ny"]
+    x, r = cells % nx, cells // nx
+    idx = torch.as_tensor((r * v.pitch + x), device=h.ws.device)  # row = z * ny + y
+    Q = 2 * p["dim"] + 1
+    out = np.empty((n, cells.size))
+    h.step(t0)
+    for j in range(n):
+        h.step(1)
+        v = h.state_view(0)
+        raw = h.ws[v.offset_bytes: v.offset_bytes + Q * v.plane_bytes].view(dt)
+        planes = raw.reshape(Q, -1)
+        out[j] = (planes[:, idx].double().sum(dim=0) / v.scale).cpu().numpy()
+    h.close()
+    return out
+
+
+def point_source(storage: str = "f32", r_fit: float | None = None, directions=((1, 0, 0),),
+                 **kw):
+    """Run the point source on the GPU library; per direction: r, |P| r and phase + k r."""
+    p = point_source_problem(**kw)
+    r_fit = p["nx"] / 4 if r_fit is None else r_fit
+    t0, n = point_source_window(p, r_fit)
+    rays = [ray_cells(p, d, r_fit) for d in directions]
+    cells = np.concatenate([c for _, c in rays])
+    P = spherical_amplitude(p, rho_probe_gpu(p, cells, t0, n, storage), t0)
+    out, j = [], 0
+    for d, (r, c) in zip(directions, rays):
+        Pd = P[j: j + c.size]
+        j += c.size
+        k = ray_wavenumber(p["omega"], p["c0"], d)
+        out.append({"direction": tuple(d), "r": r, "amp_r": np.abs(Pd) * r,
+                    "phase_kr": np.unwrap(np.angle(Pd)) + k * r, "k": k})
+    return out
 
 
 def interface_problem(nx: int = 2048, c0: float = 0.5, cp: float = 0.25, lam: float = 64.0,

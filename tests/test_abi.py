@@ -127,6 +127,31 @@ def test_check_rejects_bad_parameters(P, field, value):
     assert P.lib().lb_wave_workspace_bytes(arr, 1) == 0
 
 
+def test_check_point_source_rules(P):
+    # a point source needs periodic x and a node inside the lattice
+    from paper_2404_02346_amd import validation as V
+    p = V.point_source_problem(n=16, lam=8.0)
+    assert P.check([p]) == 0
+    assert P.check([V.point_source_problem(n=16, dim=2)]) == 0
+    arr, keep = P.make_descs([p], "f32")
+    assert arr[0].src_kind == 1 and tuple(arr[0].src_cell) == (8, 8, 8)
+    for field, value in [("xbc", 0), ("src_kind", 2), ("src_kind", -1)]:
+        arr, keep = P.make_descs([p], "f32")
+        setattr(arr[0], field, value)
+        assert P.lib().lb_wave_check(arr, 1) == -1, (field, value)
+    for cell in [(16, 0, 0), (0, -1, 0), (0, 0, 16)]:
+        arr, keep = P.make_descs([p], "f32")
+        for a in range(3):
+            arr[0].src_cell[a] = cell[a]
+        assert P.lib().lb_wave_check(arr, 1) == -1, cell
+    arr, keep = P.make_descs([V.point_source_problem(n=16, dim=2)], "f32")
+    arr[0].src_cell[2] = 1  # z must be 0 in 2D
+    assert P.lib().lb_wave_check(arr, 1) == -1
+    # descriptors without the fields set keep the sheet
+    arr, keep = P.make_descs([_cyl()], "f64")
+    assert arr[0].src_kind == 0
+
+
 def test_check_rejects_mixed_handles(P):
     arr, _ = P.make_descs([_sph(), _sph()], "f32")
     arr[1].storage = 2

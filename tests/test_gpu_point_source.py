@@ -1,0 +1,100 @@
+"""The oscillating point source (eq. waves_with_pointSource) on the GPU library.
+
+Parity: the whole state after a few dozen steps, and rho1 at probe nodes over a
+drive period of a larger cube, against the FP64 oracle element by element (2D and
+3D, FP64 and FP32, one handle holding point sources of different shapes beside a
+source-free instance).  Physics at a size the oracle would take minutes for: the
+Green's-function form of the field (1/r decay, lattice wavenumber along the axis and
+the face diagonal), as pinned for the oracle in tests/test_oracle_point_source.py.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2404_02346_amd import validation as V
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_02346_amd as P
+    P.lib()
+    return P
+
+
+def small(dim, shape, src, lam=8.0, c0=0.5):
+    p = {"dim": dim, "nx": shape[0], "ny": shape[1], "xbc": "periodic", "c0": c0,
+         "rho0": 1.0, "center": (0.0, 0.0, 0.0), "radius": 0.0, "cp": c0, "rho_a": 1.0,
+         "omega": 2 * math.pi * c0 / lam, "wall_phi": 0.99, "avg_start": 0, "src_cell": src}
+    if dim == 3:
+        p["nz"] = shape[2]
+    return p
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-13), ("f32", 2e-6)])
+def test_state_matches_oracle_in_one_batch(gpu, orc, storage, tol):
+    # two point sources of different shapes and one periodic box without a source
+    probs = [small(3, (20, 24, 28), (7, 11, 13)), small(3, (64, 16, 12), (63, 0, 11), lam=12.0),
+             small(3, (16, 8, 8), None)]
+    probs[2].pop("src_cell")
+    probs[2]["c_field"] = np.full(16 * 8 * 8, 0.5)
+    n = 45
+    h = gpu.LBWave(probs, storage=storage)
+    h.step(n)
+    for i, p in enumerate(probs):
+        ref = orc.run(p, n, want_fields=True)["fnew"]
+        got = h.get_state(i)
+        scale = max(np.abs(ref).max(), 1e-30)
+        e = np.abs(got - ref).max() / scale
+        print(f"{storage} instance {i}: max |state - oracle| / max {e:.2e}", flush=True)
+        assert e < tol
+    h.close()
+
+
+def test_2d_state_matches_oracle(gpu, orc):
+    p = small(2, (40, 36), (3, 35, 0))
+    h = gpu.LBWave([p], storage="f64")
+    h.step(60)
+    ref = orc.run(p, 60, want_fields=True)["fnew"]
+    e = np.abs(h.get_state(0) - ref).max() / np.abs(ref).max()
+    print(f"2D: {e:.2e}", flush=True)
+    assert e < 1e-13
+    h.close()
+
+
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_probe_series_matches_oracle(gpu, orc, storage, tol):
+    p = V.point_source_problem(n=64, lam=12.0)
+    t0, n = V.point_source_window(p, 16)
+    r, cells = V.ray_cells(p, (1, 0, 0), 16)
+    rd, celld = V.ray_cells(p, (1, 1, 0), 16)
+    cells = np.concatenate([cells, celld])
+    got = V.rho_probe_gpu(p, cells, t0, n, storage)
+    ref = orc.run(p, t0 + n, line=(t0, n), probes=cells)["rho_probe"]
+    e = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"{storage}: probe series vs oracle {e:.2e} over {ref.size} values", flush=True)
+    assert e < tol
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_greens_function_form_at_128(gpu, storage):
+    out = V.point_source(storage=storage, n=128, lam=16.0, r_fit=32,
+                         directions=((1, 0, 0), (1, 1, 0)))
+    amps = []
+    for o in out:
+        sel = o["r"] >= 4
+        r, ph = o["r"][sel], o["phase_kr"][sel] - o["k"] * o["r"][sel]
+        A = np.stack([np.ones_like(r), -r, 1.0 / r], axis=1)
+        c, *_ = np.linalg.lstsq(A, ph, rcond=None)
+        a = o["amp_r"][sel]
+        amps.append(a.mean())
+        print(f"{storage} {o['direction']}: k fit {c[1]:.5f} lattice {o['k']:.5f}, "
+              f"|P| r {a.min():.5f}..{a.max():.5f}", flush=True)
+        assert c[1] == pytest.approx(o["k"], rel=1.5e-3)
+        assert a.max() / a.min() - 1 < 0.02
+    assert amps[1] / amps[0] - 1 == pytest.approx(0.0, abs=0.03)
