@@ -56,10 +56,12 @@ def parse():
     ap.add_argument("--variant", default=None,
                     help="kernel variant 'cells_per_lane,x_mode,nontemporal[,steps_per_launch]' "
                          "(skips autotune)")
-    ap.add_argument("--workload", default="sphere", choices=["sphere", "batch", "surrogate"],
+    ap.add_argument("--workload", default="sphere",
+                    choices=["sphere", "batch", "surrogate", "cylinder"],
                     help="sphere: the 16-position 3D sphere (default); batch: the seeded uneven "
                          "batch of boxes (forces/s batched vs plain); surrogate: the force "
-                         "network alone (training, held-out error, inference rate)")
+                         "network alone (training, held-out error, inference rate); cylinder: "
+                         "the 2D FP64 cylinder, alone and as a batch of positions")
     ap.add_argument("--batch-seed", type=int, default=2404)
     ap.add_argument("--batch-n", type=int, default=256)
     ap.add_argument("--graph", type=int, default=64,
@@ -245,6 +247,53 @@ def batch_workload(args):
     print(json.dumps(out), flush=True)
 
 
+def cylinder_workload(args):
+    """The 2D FP64 cylinder (128 x 64 D2Q5, 5120 steps): one box alone, then 64 positions in one
+    handle; the single box's force against the oracle's (the oracle runs on the host cores)."""
+    import torch
+    import paper_2404_02346_amd as P
+    import workloads
+    torch.cuda.set_device(0)
+    lam, c0 = 128.0, 0.5
+    cal = P.cavity_calibrate(128, c0, 2 * math.pi * c0 / lam)
+    p = workloads.cylinder_2d(cal["x_mid"], cal["k"])
+    n_steps, cells = int(p["n_steps"]), 128 * 64
+    out = {"mode": "cylinder", "dtype": "f64",
+           "config": {"workload": "2D cylinder, D2Q5 128x64, lambda=128, c0=0.5, c_p/c0=1.2, R=8, "
+                                  "64 surface points, kh=pi/4, 20 periods (5120 steps), average "
+                                  "over the last 5"}}
+    for n_inst in (1, 64):
+        probs = [p] if n_inst == 1 else [
+            workloads.cylinder_2d(cal["x_mid"], cal["k"], kh=j * (math.pi / 2) / (n_inst - 1))
+            for j in range(n_inst)]
+        h = P.LBWave(probs, storage="f64")
+        h.autotune(4)
+        h.set_graph(args.graph)
+        h.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h.step(n_steps)
+        F, _ = h.force()
+        dt = time.perf_counter() - t0
+        h.close()
+        key = "single" if n_inst == 1 else f"batch_{n_inst}"
+        out[key] = {"seconds": round(dt, 4), "ms_per_step": round(dt / n_steps * 1e3, 5),
+                    "mlups": round(n_inst * cells * n_steps / dt / 1e6, 1),
+                    "forces_per_s": round(n_inst / dt, 2)}
+        if n_inst == 1:
+            out["force_x"] = float(F[0, 0])
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        ref = oracle.run(p, n_steps)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(cells * n_steps / dt / 1e6, 1), "unit": "MLUPS",
+                               "kind": "oracle", "sample": "the whole 5120-step run",
+                               "force_x": float(ref["F_avg"][0]),
+                               "gpu_vs_oracle_rel": abs(out["force_x"] / ref["F_avg"][0] - 1)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -254,6 +303,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch":
         batch_workload(args)
+        return
+    if args.workload == "cylinder":
+        cylinder_workload(args)
         return
     if args.workload == "surrogate":
         import torch

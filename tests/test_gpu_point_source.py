@@ -98,3 +98,22 @@ def test_greens_function_form_at_128(gpu, storage):
         assert c[1] == pytest.approx(o["k"], rel=1.5e-3)
         assert a.max() / a.min() - 1 < 0.02
     assert amps[1] / amps[0] - 1 == pytest.approx(0.0, abs=0.03)
+
+
+def test_point_source_handles_keep_one_step_per_launch(gpu, orc):
+    # the source node is imposed between launches, so two steps per launch are refused, autotune
+    # keeps one, and a graph-replayed run still matches the oracle
+    p = V.point_source_problem(n=32, lam=8.0)
+    h = gpu.LBWave([p], storage="f32")
+    with pytest.raises(gpu.LBError):
+        h.set_steps_per_launch(2)
+    h.autotune(2)
+    assert h.steps_per_launch() == 1
+    h.reset()
+    h.set_graph(16)
+    h.step(70)
+    ref = orc.run(p, 70, want_fields=True)["fnew"]
+    e = np.abs(h.get_state(0) - ref).max() / np.abs(ref).max()
+    print(f"after autotune, graph replay: {e:.2e}", flush=True)
+    assert e < 2e-6
+    h.close()
