@@ -334,6 +334,29 @@ def test_full_size_sphere_fields(P, orc):
     assert ef <= TOL_FIELD["f32"] and et <= TOL_TRACE["f32"]
 
 
+def test_non_finite_force_is_reported_until_reset(P):
+    # a NaN state (set from the host) makes the measured force non-finite: the force read-out
+    # and the next step report LB_ENAN, and a reset clears it
+    p = driven_object(2, (10, 40), R=2.0, n_surf=16, avg_start=0)
+    h = P.LBWave([p], storage="f64")
+    h.step(4)
+    st = h.get_state(0)
+    st[:] = np.nan
+    h.set_state(0, st)
+    h.step(3)
+    with pytest.raises(P.LBError) as ei:
+        h.force()
+    assert ei.value.code == -6
+    with pytest.raises(P.LBError) as ei:
+        h.step(1)
+    assert ei.value.code == -6
+    h.reset()
+    h.step(6)
+    F, nacc = h.force()
+    assert nacc[0] == 6 and np.all(np.isfinite(F))
+    h.close()
+
+
 def test_step_zero_and_errors(P):
     p = driven_object(2, (10, 40), R=2.0, n_surf=16, avg_start=0)
     h = P.LBWave([p], storage="f64")

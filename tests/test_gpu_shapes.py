@@ -1,14 +1,16 @@
 """Objects of other shapes (workloads/shapes.py) on the GPU library.
 
-* Parity: an ellipsoid given as a per-cell sound-speed field with a
-  triangle-mesh integration surface, GPU against the FP64 oracle element by
-  element (one and two steps per launch).
+* Parity: an ellipsoid, and a non-convex peanut whose sound speed comes from
+  the signed distance to its triangle mesh, each given as a per-cell
+  sound-speed field with a triangle-mesh integration surface, GPU against the
+  FP64 oracle element by element (one and two steps per launch).
 * Physics: a density-matched object scatters as a monopole to leading order
   in kR, so its force depends on its volume, not its shape: prolate and
   oblate ellipsoids of the sphere's volume, in any orientation, feel the
   sphere's force within the finite-kR and resolution error (kR = 0.12 here),
-  with no transverse force.  The mesh-integrated sphere must also agree with
-  the Fibonacci-integrated one.
+  with no transverse force; so does the non-convex peanut of the sphere's
+  volume, with its lobes along x or along y.  The mesh-integrated sphere must
+  also agree with the Fibonacci-integrated one.
 """
 import math
 
@@ -51,13 +53,20 @@ def small_ellipsoid():
     return shapes.ellipsoid_problem(base, (5.0, 3.0, 2.5), level=3)
 
 
+def small_peanut():
+    base = small_ellipsoid()
+    V, F = shapes.peanut(4.5, 0.3, level=2)
+    return shapes.mesh_problem(base, V, F)
+
+
+@pytest.mark.parametrize("shape", ["ellipsoid", "peanut"])
 @pytest.mark.parametrize("storage,spl,tol", [("f64", 1, 1e-12), ("f64", 2, 1e-12),
                                              ("f32", 1, 2e-5), ("f32", 2, 2e-5)])
-def test_ellipsoid_parity(P, orc, storage, spl, tol):
-    p = small_ellipsoid()
+def test_ellipsoid_parity(P, orc, shape, storage, spl, tol):
+    p = small_ellipsoid() if shape == "ellipsoid" else small_peanut()
     n = 20
     init = workloads.random_state(91, p["nx"] * p["ny"] * p["nz"], 7)
-    say(f"ellipsoid parity {storage}, {spl} steps per launch, {len(p['surf_area'])} elements")
+    say(f"{shape} parity {storage}, {spl} steps per launch, {len(p['surf_area'])} elements")
     ref = orc.run(p, n, fnew_init=init, want_fields=True, want_trace=True)
     h = P.LBWave([p], storage=storage, trace_steps=n)
     h.set_steps_per_launch(spl)
@@ -79,6 +88,14 @@ def test_force_depends_on_volume_not_shape(P):
     shapes_axes = {"sphere (mesh)": (5.0, 5.0, 5.0), "prolate along x": (7.5, b, b),
                    "prolate along y": (b, 7.5, b), "oblate, thin along x": (3.2, 6.25, 6.25)}
     probs = [sphere] + [shapes.ellipsoid_problem(sphere, ax, level=4) for ax in shapes_axes.values()]
+    # the non-convex peanut of the sphere's volume, lobes along x, then turned to lie along y
+    V1, F1 = shapes.peanut(1.0, 0.3, level=3)
+    Rp = (4.0 / 3.0 * math.pi * 125.0 / shapes.mesh_volume(V1, F1)) ** (1.0 / 3.0)
+    PV, PF = shapes.peanut(Rp, 0.3, level=3)
+    PVy = np.stack([-PV[:, 1], PV[:, 0], PV[:, 2]], axis=1)       # 90 degrees about z
+    shapes_axes["peanut, lobes along x"] = f"R = {Rp:.3f}"
+    shapes_axes["peanut, lobes along y"] = f"R = {Rp:.3f}"
+    probs += [shapes.mesh_problem(sphere, PV, PF), shapes.mesh_problem(sphere, PVy, PF)]
     h = P.LBWave(probs, storage="f32")
     h.autotune(2)
     h.set_graph(64)
