@@ -571,25 +571,35 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
 #pragma unroll
     for (int j = 0; j < R; ++j) Q0[j] = Qpx[j] = Qmx[j] = Qpy[j] = Qmy[j] = Qpz[j] = Qpz2[j] = C(0);
 
-    // the seven pulled populations (step t) of row y0 + j of plane zq; the
-    // +x / -x neighbours by loads offset by one element
-    auto load_row = [&](int zq, int j, E *f) {
-        const int zm = (zq == 0) ? nz - 1 : zq - 1;
-        const int zn = (zq == nz - 1) ? 0 : zq + 1;
+    // uniform offsets, once per block: rows y0 - 1 .. y0 + R (wrapped in y) and their -y / +y
+    // neighbours within a plane, and the plane size; per plane only the z bases change
+    const int64_t zstride = (int64_t)ny * pitch;
+    int64_t yoff[R + 2], ymoff[R + 2], ynoff[R + 2];
+#pragma unroll
+    for (int j = -1; j <= R; ++j) {
         int y = y0 + j;
         y = (y < 0) ? y + ny : (y >= ny ? y - ny : y);
-        const int ym = (y == 0) ? ny - 1 : y - 1;
-        const int yn = (y == ny - 1) ? 0 : y + 1;
-        if (xin) {
-            const int64_t row = ((int64_t)zq * ny + y) * pitch;
-            f[0] = *at(src + row, ux);
-            f[1] = *at(src + plane + row - 1, ux);
-            f[2] = *at(src + 2 * plane + row + 1, ux);
-            f[3] = *at(src + 3 * plane + ((int64_t)zq * ny + ym) * pitch, ux);
-            f[4] = *at(src + 4 * plane + ((int64_t)zq * ny + yn) * pitch, ux);
-            f[5] = *at(src + 5 * plane + ((int64_t)zm * ny + y) * pitch, ux);
-            f[6] = *at(src + 6 * plane + ((int64_t)zn * ny + y) * pitch, ux);
-        }
+        yoff[j + 1] = (int64_t)y * pitch;
+        ymoff[j + 1] = (int64_t)((y == 0) ? ny - 1 : y - 1) * pitch;
+        ynoff[j + 1] = (int64_t)((y == ny - 1) ? 0 : y + 1) * pitch;
+    }
+
+    // the seven pulled populations (step t) of row y0 + j of plane zq; the
+    // +x / -x neighbours by loads offset by one element.  Every lane loads: x < pitch keeps
+    // the row inside the buffer (padding cells hold zeros), the -1 / +1 offsets stay inside
+    // because the +x plane follows plane 0 and the -x plane precedes plane 3
+    auto load_row = [&](int zq, int j, E *f) {
+        const int64_t zb = zq * zstride;
+        const int64_t zbm = ((zq == 0) ? nz - 1 : zq - 1) * zstride;
+        const int64_t zbn = ((zq == nz - 1) ? 0 : zq + 1) * zstride;
+        const int64_t row = zb + yoff[j + 1];
+        f[0] = *at(src + row, ux);
+        f[1] = *at(src + plane + row - 1, ux);
+        f[2] = *at(src + 2 * plane + row + 1, ux);
+        f[3] = *at(src + 3 * plane + zb + ymoff[j + 1], ux);
+        f[4] = *at(src + 4 * plane + zb + ynoff[j + 1], ux);
+        f[5] = *at(src + 5 * plane + zbm + yoff[j + 1], ux);
+        f[6] = *at(src + 6 * plane + zbn + yoff[j + 1], ux);
     };
     auto load_plane = [&](int zq, E (&L)[R + 2][7]) {
 #pragma unroll
@@ -622,25 +632,21 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
             E Lrow[7];
             if constexpr (!PF) load_row(zp, j, Lrow);
             const E *L = PF ? Lcur[j + 1] : Lrow;
+            // every lane computes (padding lanes on zeros); lanes beyond the row pass on zeros
             C f[7], o[7];
-            if (xin) {
 #pragma unroll
-                for (int i = 0; i < 7; ++i) f[i] = T::to_c(L[i]);
-                if (x == 0) f[1] = C(0);       // nothing enters from outside the sheets
-                if (x == nx - 1) f[2] = C(0);
-                C rho = f[0];
+            for (int i = 0; i < 7; ++i) f[i] = T::to_c(L[i]);
+            if (x == 0) f[1] = C(0);       // nothing enters from outside the sheets
+            if (x == nx - 1) f[2] = C(0);
+            C rho = f[0];
 #pragma unroll
-                for (int i = 1; i < 7; ++i) rho += f[i];
-                if (meas && own_plane && j >= 0 && j < R)
-                    store_moments(mom_a, box_row(mb_lo, mb_n, y, zp), mb_lo[0], mb_n[0], x, rho, f);
-                const C c2 = c2_at(c2box, box_row(bb_lo, bb_n, y, zp), bb_lo[0], bb_n[0], c0sq, x);
-                cell_rule<3, C>(f, rho, c2, x, nx, true, phi, rs_a, o);
+            for (int i = 1; i < 7; ++i) rho += f[i];
+            if (meas && own_plane && j >= 0 && j < R && xin)
+                store_moments(mom_a, box_row(mb_lo, mb_n, y, zp), mb_lo[0], mb_n[0], x, rho, f);
+            const C c2 = c2_at(c2box, box_row(bb_lo, bb_n, y, zp), bb_lo[0], bb_n[0], c0sq, x);
+            cell_rule<3, C>(f, rho, c2, x, nx, true, phi, rs_a, o);
 #pragma unroll
-                for (int i = 0; i < 7; ++i) o[i] = T::to_c(T::to_r(o[i]));
-            } else {
-#pragma unroll
-                for (int i = 0; i < 7; ++i) o[i] = C(0);
-            }
+            for (int i = 0; i < 7; ++i) o[i] = xin ? T::to_c(T::to_r(o[i])) : C(0);
             if (j >= 0 && j < R) {
                 N0[j] = o[0];
                 Npx[j] = __shfl_up(o[1], 1);    // +x arrives from x - 1
@@ -682,7 +688,7 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
                     store_moments(mom_b, box_row(mb_lo, mb_n, y, zq), mb_lo[0], mb_n[0], x, rho, f);
                 const C c2 = c2_at(c2box, box_row(bb_lo, bb_n, y, zq), bb_lo[0], bb_n[0], c0sq, x);
                 cell_rule<3, C>(f, rho, c2, x, nx, true, phi, rs_b, o);
-                const int64_t row = ((int64_t)zq * ny + y) * pitch;
+                const int64_t row = zq * zstride + yoff[j + 1];
 #pragma unroll
                 for (int i = 0; i < 7; ++i)
                     vstore<E, (NT >= 1)>(at(dst + (i * plane + row), ux), T::to_r(o[i]));
