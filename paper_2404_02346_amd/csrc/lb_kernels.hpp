@@ -575,6 +575,9 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
     // neighbours within a plane, and the plane size; per plane only the z bases change
     const int64_t zstride = (int64_t)ny * pitch;
     int64_t yoff[R + 2], ymoff[R + 2], ynoff[R + 2];
+    // and the y part of the moment-box and sound-speed-box row indices (-1: row outside the box;
+    // box_row's index (bz n1 + by) n0 is the sum of a y part and a z part)
+    int mb_y[R + 2], bb_y[R + 2];
 #pragma unroll
     for (int j = -1; j <= R; ++j) {
         int y = y0 + j;
@@ -582,7 +585,17 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
         yoff[j + 1] = (int64_t)y * pitch;
         ymoff[j + 1] = (int64_t)((y == 0) ? ny - 1 : y - 1) * pitch;
         ynoff[j + 1] = (int64_t)((y == ny - 1) ? 0 : y + 1) * pitch;
+        const int mby = y - mb_lo[1], bby = y - bb_lo[1];
+        mb_y[j + 1] = (mb_n[0] > 0 && mby >= 0 && mby < mb_n[1]) ? mby * mb_n[0] : -1;
+        bb_y[j + 1] = (bb_n[0] > 0 && bby >= 0 && bby < bb_n[1]) ? bby * bb_n[0] : -1;
     }
+    auto box_z = [&](const int *lo, const int *n, int z) {
+        const int bz = z - lo[2];
+        return (n[0] > 0 && bz >= 0 && bz < n[2]) ? bz * n[1] * n[0] : -1;
+    };
+    auto box_rowj = [&](const int *ypart, int zpart, int j) {
+        return (zpart >= 0 && ypart[j + 1] >= 0) ? zpart + ypart[j + 1] : -1;
+    };
 
     // the seven pulled populations (step t) of row y0 + j of plane zq; the
     // +x / -x neighbours by loads offset by one element.  Every lane loads: x < pitch keeps
@@ -625,10 +638,9 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
         }
         C N0[R], Npx[R], Nmx[R], Npy[R], Nmy[R], Npz[R], Nmz[R];
         C prev_py = C(0);
+        const int mb_z = box_z(mb_lo, mb_n, zp), bb_z = box_z(bb_lo, bb_n, zp);
 #pragma unroll
         for (int j = -1; j <= R; ++j) {
-            int y = y0 + j;
-            y = (y < 0) ? y + ny : (y >= ny ? y - ny : y);
             E Lrow[7];
             if constexpr (!PF) load_row(zp, j, Lrow);
             const E *L = PF ? Lcur[j + 1] : Lrow;
@@ -642,8 +654,8 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
 #pragma unroll
             for (int i = 1; i < 7; ++i) rho += f[i];
             if (meas && own_plane && j >= 0 && j < R && xin)
-                store_moments(mom_a, box_row(mb_lo, mb_n, y, zp), mb_lo[0], mb_n[0], x, rho, f);
-            const C c2 = c2_at(c2box, box_row(bb_lo, bb_n, y, zp), bb_lo[0], bb_n[0], c0sq, x);
+                store_moments(mom_a, box_rowj(mb_y, mb_z, j), mb_lo[0], mb_n[0], x, rho, f);
+            const C c2 = c2_at(c2box, box_rowj(bb_y, bb_z, j), bb_lo[0], bb_n[0], c0sq, x);
             cell_rule<3, C>(f, rho, c2, x, nx, true, phi, rs_a, o);
 #pragma unroll
             for (int i = 0; i < 7; ++i) o[i] = xin ? T::to_c(T::to_r(o[i])) : C(0);
@@ -670,9 +682,9 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
         if (p >= 1 && xin) {
             // step t + 1 on plane zq = z0 + p - 1
             const int zq = z0 + p - 1;
+            const int mb_zq = box_z(mb_lo, mb_n, zq), bb_zq = box_z(bb_lo, bb_n, zq);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
-                const int y = y0 + j;
                 C f[7], o[7];
                 f[0] = Q0[j];
                 f[1] = (x == 0) ? C(0) : Qpx[j];
@@ -685,8 +697,8 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
 #pragma unroll
                 for (int i = 1; i < 7; ++i) rho += f[i];
                 if (meas)
-                    store_moments(mom_b, box_row(mb_lo, mb_n, y, zq), mb_lo[0], mb_n[0], x, rho, f);
-                const C c2 = c2_at(c2box, box_row(bb_lo, bb_n, y, zq), bb_lo[0], bb_n[0], c0sq, x);
+                    store_moments(mom_b, box_rowj(mb_y, mb_zq, j), mb_lo[0], mb_n[0], x, rho, f);
+                const C c2 = c2_at(c2box, box_rowj(bb_y, bb_zq, j), bb_lo[0], bb_n[0], c0sq, x);
                 cell_rule<3, C>(f, rho, c2, x, nx, true, phi, rs_b, o);
                 const int64_t row = zq * zstride + yoff[j + 1];
 #pragma unroll
