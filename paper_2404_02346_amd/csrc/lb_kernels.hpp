@@ -153,7 +153,7 @@ struct InstDev {
     double c0sq;             // fluid c0^2 (outside the box)
     int32_t bb_lo[3];        // sound-speed box origin
     int32_t bb_n[3];         // sound-speed box extent (0 -> no box)
-    const void *c2box;       // c^2 over the box in the compute type, x fastest
+    const void *c2box;       // c^2 over the box in the compute type, x fastest, then c0^2
     double src_amp;          // rho_a times the storage scale
     double omega, wall_phi;
     int64_t max_steps;       // frozen for t >= max_steps
@@ -507,14 +507,6 @@ __device__ inline void store_moments(gptr<C> mom, int mrow, int mb_lo0, int mb_n
     }
 }
 
-template <typename C>
-__device__ inline C c2_at(gptr<const C> c2box, int crow, int bb_lo0, int bb_n0, C c0sq, int x)
-{
-    const int bx = x - bb_lo0;
-    if (crow >= 0 && bx >= 0 && bx < bb_n0) return c2box[crow + bx];
-    return c0sq;
-}
-
 template <typename S, int R, int NT, bool PF>
 __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const int bsrc, int lb,
                                       typename StoreTraits<S>::C (*xe)[4][R][2])
@@ -596,6 +588,20 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
     auto box_rowj = [&](const int *ypart, int zpart, int j) {
         return (zpart >= 0 && ypart[j + 1] >= 0) ? zpart + ypart[j + 1] : -1;
     };
+    // c^2 of the lane's cell in rows y0 - 1 .. y0 + R of plane zq: every lane loads, cells
+    // outside the sound-speed box read the c0^2 stored after it.  Loaded a plane ahead with the
+    // populations, so that no load is waited for right after it is issued
+    const int n_box = bb_n[0] * bb_n[1] * bb_n[2];
+    auto load_c2 = [&](int zq, C (&c)[R + 2]) {
+        const int bz = box_z(bb_lo, bb_n, zq);
+        const int bx = x - bb_lo[0];
+        const bool xb = bx >= 0 && bx < bb_n[0];
+#pragma unroll
+        for (int j = -1; j <= R; ++j) {
+            const int crow = box_rowj(bb_y, bz, j);
+            c[j + 1] = c2box[(crow >= 0 && xb) ? crow + bx : n_box];
+        }
+    };
 
     // the seven pulled populations (step t) of row y0 + j of plane zq; the
     // +x / -x neighbours by loads offset by one element.  Every lane loads: x < pitch keeps
@@ -622,23 +628,38 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
 
     // PF: the loads of plane p + 1 are in flight while plane p is computed
     E Lnext[R + 2][7];
-    if (PF) load_plane(wrapz(z0 - 1), Lnext);
+    C C2next[R + 2];
+    if (PF) {
+        load_plane(wrapz(z0 - 1), Lnext);
+        load_c2(wrapz(z0 - 1), C2next);
+    }
+    C C2prev[R];  // c^2 of the owned rows of plane p - 1 (step t + 1)
+#pragma unroll
+    for (int j = 0; j < R; ++j) C2prev[j] = c0sq;
 
     for (int p = -1; p <= zlen; ++p) {
         const int zp = wrapz(z0 + p);
         const bool own_plane = p >= 0 && p < zlen;
         const int sl = (p + 2) & 1;
         E Lcur[R + 2][7];
+        C C2cur[R + 2];
         if (PF) {
 #pragma unroll
-            for (int j = 0; j < R + 2; ++j)
+            for (int j = 0; j < R + 2; ++j) {
 #pragma unroll
                 for (int i = 0; i < 7; ++i) Lcur[j][i] = Lnext[j][i];
-            if (p < zlen) load_plane(wrapz(z0 + p + 1), Lnext);
+                C2cur[j] = C2next[j];
+            }
+            if (p < zlen) {
+                load_plane(wrapz(z0 + p + 1), Lnext);
+                load_c2(wrapz(z0 + p + 1), C2next);
+            }
+        } else {
+            load_c2(zp, C2cur);
         }
         C N0[R], Npx[R], Nmx[R], Npy[R], Nmy[R], Npz[R], Nmz[R];
         C prev_py = C(0);
-        const int mb_z = box_z(mb_lo, mb_n, zp), bb_z = box_z(bb_lo, bb_n, zp);
+        const int mb_z = box_z(mb_lo, mb_n, zp);
 #pragma unroll
         for (int j = -1; j <= R; ++j) {
             E Lrow[7];
@@ -655,8 +676,7 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
             for (int i = 1; i < 7; ++i) rho += f[i];
             if (meas && own_plane && j >= 0 && j < R && xin)
                 store_moments(mom_a, box_rowj(mb_y, mb_z, j), mb_lo[0], mb_n[0], x, rho, f);
-            const C c2 = c2_at(c2box, box_rowj(bb_y, bb_z, j), bb_lo[0], bb_n[0], c0sq, x);
-            cell_rule<3, C>(f, rho, c2, x, nx, true, phi, rs_a, o);
+            cell_rule<3, C>(f, rho, C2cur[j + 1], x, nx, true, phi, rs_a, o);
 #pragma unroll
             for (int i = 0; i < 7; ++i) o[i] = xin ? T::to_c(T::to_r(o[i])) : C(0);
             if (j >= 0 && j < R) {
@@ -682,7 +702,7 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
         if (p >= 1 && xin) {
             // step t + 1 on plane zq = z0 + p - 1
             const int zq = z0 + p - 1;
-            const int mb_zq = box_z(mb_lo, mb_n, zq), bb_zq = box_z(bb_lo, bb_n, zq);
+            const int mb_zq = box_z(mb_lo, mb_n, zq);
 #pragma unroll
             for (int j = 0; j < R; ++j) {
                 C f[7], o[7];
@@ -698,8 +718,7 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
                 for (int i = 1; i < 7; ++i) rho += f[i];
                 if (meas)
                     store_moments(mom_b, box_rowj(mb_y, mb_zq, j), mb_lo[0], mb_n[0], x, rho, f);
-                const C c2 = c2_at(c2box, box_rowj(bb_y, bb_zq, j), bb_lo[0], bb_n[0], c0sq, x);
-                cell_rule<3, C>(f, rho, c2, x, nx, true, phi, rs_b, o);
+                cell_rule<3, C>(f, rho, C2prev[j], x, nx, true, phi, rs_b, o);
                 const int64_t row = zq * zstride + yoff[j + 1];
 #pragma unroll
                 for (int i = 0; i < 7; ++i)
@@ -708,6 +727,7 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
         }
 #pragma unroll
         for (int j = 0; j < R; ++j) {
+            C2prev[j] = C2cur[j + 1];
             Qpz2[j] = Qpz[j];
             Q0[j] = N0[j];
             Qpx[j] = Npx[j];
@@ -879,7 +899,7 @@ __device__ inline int xcd_block(int b, int n)
 }
 
 template <typename S, int R, int NT, bool PF>
-__global__ void __launch_bounds__(kStepThreads, PF ? 3 : 4) step2_kernel(StepArgs a)
+__global__ void __launch_bounds__(kStepThreads, PF ? 2 : 4) step2_kernel(StepArgs a)
 {
     using C = typename StoreTraits<S>::C;
     __shared__ double lds[4][64][4];

@@ -372,8 +372,8 @@ Layout plan(const lb_wave_desc *descs, int n)
         off = align_up(off + sizeof(double) * kNumSlot * 4 * (size_t)P.n_chunks);
         P.off_trace = off;
         off = align_up(off + sizeof(double) * 3 * (size_t)d.trace_steps);
-        P.off_box = off;
-        off = align_up(off + compute_bytes(d.storage) * P.box.cells());
+        P.off_box = off;  // the box, then one c0^2 sentinel for reads from outside it
+        off = align_up(off + compute_bytes(d.storage) * (P.box.cells() + 1));
         for (int b = 0; b < kNumBuf; ++b) {
             P.off_buf[b] = off;
             off = align_up(off + elem_bytes(d.storage) * (size_t)P.plane * Q);
@@ -968,10 +968,10 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
             host_blobs.push_back(std::move(blob));
             blob_off.push_back(P.off_surf);
         }
-        // compact c^2 table in the compute type
-        if (P.box.cells() > 0) {
+        // compact c^2 table in the compute type, followed by the c0^2 sentinel
+        {
             const size_t cb = compute_bytes(d.storage);
-            std::vector<uint8_t> blob(cb * P.box.cells());
+            std::vector<uint8_t> blob(cb * (P.box.cells() + 1));
             size_t q = 0;
             for (int z = 0; z < P.box.n[2]; ++z)
                 for (int y = 0; y < P.box.n[1]; ++y)
@@ -990,6 +990,13 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
                             std::memcpy(blob.data() + 4 * q, &f, 4);
                         }
                     }
+            const double s2 = d.c0 * d.c0;  // rounded as the kernels round c0^2
+            if (cb == 8) {
+                std::memcpy(blob.data() + 8 * q, &s2, 8);
+            } else {
+                const float f = (float)s2;
+                std::memcpy(blob.data() + 4 * q, &f, 4);
+            }
             host_blobs.push_back(std::move(blob));
             blob_off.push_back(P.off_box);
         }
