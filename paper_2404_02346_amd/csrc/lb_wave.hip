@@ -570,8 +570,10 @@ void launch_point(const lb_wave *h, const StepArgs &a, hipStream_t st)
     }
 }
 
-// Rows per row group of the two-step kernel (FP64 holds twice the registers).
-int two_step_rows(int storage) { return storage == LB_F64 ? 2 : 4; }
+// Rows per row group of the two-step kernel: 4 for FP32; 2 for FP64, whose values take
+// twice the registers, and for FP16/BF16, whose 2-byte loads are latency-bound and gain
+// more from the extra wavefronts than they lose to the re-read halo rows (measured).
+int two_step_rows(int storage) { return storage == LB_F32 ? 4 : 2; }
 // Two-step plane chunks shrink (down to kMinZChunk) until a handle has this
 // many blocks: 256 CUs hold 1024 of them at four wavefronts per SIMD.
 constexpr int64_t kMinBlocks2 = 1024;
@@ -595,8 +597,8 @@ void launch2(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
     switch (h->storage) {
     case LB_F64: launch2_t<double, 2>(h, a, blocks, st); break;
     case LB_F32: launch2_t<float, 4>(h, a, blocks, st); break;
-    case LB_F16: launch2_t<_Float16, 4>(h, a, blocks, st); break;
-    default: launch2_t<bf16, 4>(h, a, blocks, st); break;
+    case LB_F16: launch2_t<_Float16, 2>(h, a, blocks, st); break;
+    default: launch2_t<bf16, 2>(h, a, blocks, st); break;
     }
 }
 
