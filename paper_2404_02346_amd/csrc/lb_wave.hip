@@ -575,12 +575,14 @@ void launch_point(const lb_wave *h, const StepArgs &a, hipStream_t st)
 // more from the extra wavefronts than they lose to the re-read halo rows (measured).
 int two_step_rows(int storage) { return storage == LB_F32 ? 4 : 2; }
 // Two-step plane chunks shrink (down to kMinZChunk) until a handle has this
-// many blocks: 256 CUs hold 1024 of them at four wavefronts per SIMD.
+// many blocks: two rounds of the 512 that 256 CUs hold at two wavefronts per
+// SIMD (one round for FP64 at four).
 constexpr int64_t kMinBlocks2 = 1024;
 constexpr int kMinZChunk = 4;
 
-// Prefetching the next plane's loads pays where the registers allow it
-// (4- and 2-byte storage: three wavefronts per SIMD); FP64 loads in place.
+// Prefetching the next plane's populations and sound speeds pays where the
+// registers allow it (4- and 2-byte storage, two wavefronts per SIMD without
+// spills); FP64 loads in place.
 template <typename S, int R>
 void launch2_t(const lb_wave *h, const StepArgs &a, int blocks, hipStream_t st)
 {
