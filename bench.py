@@ -297,7 +297,7 @@ def cylinder_workload(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(the batched instances would shard by instance; see the design notes)",
               file=sys.stderr)
         sys.exit(2)
