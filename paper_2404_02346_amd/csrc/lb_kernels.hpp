@@ -604,21 +604,24 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
     };
 
     // the seven pulled populations (step t) of row y0 + j of plane zq; the
-    // +x / -x neighbours by loads offset by one element.  Every lane loads: x < pitch keeps
-    // the row inside the buffer (padding cells hold zeros), the -1 / +1 offsets stay inside
+    // +x / -x neighbours by loads offset by one element.  Every lane loads (no branch, so no
+    // wait is forced early): lanes without a cell (padding, or the idle wavefront of a
+    // 3-wavefront row) read x = 0 of the same row, a line the row's first wavefront fetches
+    // anyway, and their results are discarded; the -1 / +1 offsets stay inside the buffer
     // because the +x plane follows plane 0 and the -x plane precedes plane 3
+    const uint32_t uxl = xin ? ux : 0u;
     auto load_row = [&](int zq, int j, E *f) {
         const int64_t zb = zq * zstride;
         const int64_t zbm = ((zq == 0) ? nz - 1 : zq - 1) * zstride;
         const int64_t zbn = ((zq == nz - 1) ? 0 : zq + 1) * zstride;
         const int64_t row = zb + yoff[j + 1];
-        f[0] = *at(src + row, ux);
-        f[1] = *at(src + plane + row - 1, ux);
-        f[2] = *at(src + 2 * plane + row + 1, ux);
-        f[3] = *at(src + 3 * plane + zb + ymoff[j + 1], ux);
-        f[4] = *at(src + 4 * plane + zb + ynoff[j + 1], ux);
-        f[5] = *at(src + 5 * plane + zbm + yoff[j + 1], ux);
-        f[6] = *at(src + 6 * plane + zbn + yoff[j + 1], ux);
+        f[0] = *at(src + row, uxl);
+        f[1] = *at(src + plane + row - 1, uxl);
+        f[2] = *at(src + 2 * plane + row + 1, uxl);
+        f[3] = *at(src + 3 * plane + zb + ymoff[j + 1], uxl);
+        f[4] = *at(src + 4 * plane + zb + ynoff[j + 1], uxl);
+        f[5] = *at(src + 5 * plane + zbm + yoff[j + 1], uxl);
+        f[6] = *at(src + 6 * plane + zbn + yoff[j + 1], uxl);
     };
     auto load_plane = [&](int zq, E (&L)[R + 2][7]) {
 #pragma unroll
