@@ -94,7 +94,7 @@ int lb_mlp_mfma_probe(const uint16_t *dev_A, const uint16_t *dev_B, float *dev_D
  * exact (erf) GELU, or with derivative != 0 its derivative g'(z) = Phi(z) +
  * z phi(z), in the FP32 form every layer uses (Phi from Hastings' rational-
  * exponential erf, within 3e-7 of the exact value).  dev_z and dev_out hold n
- * FP32 values (0 <= n <= 2^40; they may alias).  Asynchronous on hip_stream.
+ * FP32 values (0 <= n <= 2^31; they may alias).  Asynchronous on hip_stream.
  * LB_EINVAL for a negative or too large n or a NULL pointer with n > 0. */
 int lb_mlp_activation(const float *dev_z, int64_t n, int32_t derivative, float *dev_out,
                       void *hip_stream);

@@ -784,7 +784,8 @@ int lb_mlp_activation(const float *dev_z, int64_t n, int32_t derivative, float *
 {
     if (n < 0 || (n > 0 && (!dev_z || !dev_out)))
         return lbw_fail_msg(LB_EINVAL, "activation: bad arguments");
-    if (n > ((int64_t)1 << 40)) return lbw_fail_msg(LB_EINVAL, "activation: n too large");
+    // one thread per value in a 1D grid, whose thread count must fit 32 bits
+    if (n > ((int64_t)1 << 31)) return lbw_fail_msg(LB_EINVAL, "activation: n above 2^31");
     if (n == 0) return LB_OK;
     const int64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(activation_kernel, dim3((unsigned)blocks), dim3(256), 0,

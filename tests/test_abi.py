@@ -215,3 +215,5 @@ def test_mlp_sizes_and_argument_errors(P):
     assert lib.lb_mlp_activation(None, -1, 0, None, None) == -1
     assert lib.lb_mlp_activation(None, 5, 0, None, None) == -1
     assert lib.lb_mlp_activation(None, 0, 1, None, None) == 0  # nothing to do, no device call
+    assert lib.lb_mlp_activation(ctypes.c_void_p(256), (1 << 31) + 1, 0, ctypes.c_void_p(256),
+                                 None) == -1              # beyond the 32-bit grid
