@@ -57,8 +57,8 @@ int lb_mlp_destroy(lb_mlp *h);  /* NULL-safe */
 int lb_mlp_set_params(lb_mlp *h, const float *host_params);
 int lb_mlp_get_params(lb_mlp *h, float *host_params);
 
-/* y = net(x) for B >= 1 samples (any B: inference keeps no activations in
- * the workspace): dev_x B x 4 FP32, dev_y B FP32.  One fused launch carries
+/* y = net(x) for 1 <= B <= 2^30 samples (independent of max_batch: inference
+ * keeps no activations in the workspace): dev_x B x 4 FP32, dev_y B FP32.  One fused launch carries
  * 128 samples per workgroup through every layer with the activations in LDS;
  * operand roundings as in the training forward (BF16 weights and
  * activations, FP32 accumulation and bias).  Asynchronous on the handle's

@@ -315,6 +315,8 @@ __global__ void __launch_bounds__(64) mfma_probe_kernel(const uint16_t *A, const
 constexpr int kInferRows = 128;
 constexpr int kInferWaves = 8;
 constexpr int kInferThreads = 64 * kInferWaves;
+// the 1D grid of ceil(B / kInferRows) blocks must hold fewer than 2^32 threads
+constexpr int kMaxInferBatch = 1 << 30;
 constexpr int kActLd = kHidden + 8;
 
 __global__ void __launch_bounds__(kInferThreads, kInferWaves / 2)
@@ -705,6 +707,7 @@ int lb_mlp_forward(lb_mlp *h, const float *dev_x, int32_t B, float *dev_y)
 {
     if (!h) return lbw_fail_msg(LB_EINVAL, "handle is NULL");
     if (B < 1) return lbw_fail_msg(LB_EINVAL, "batch must be >= 1");
+    if (B > kMaxInferBatch) return lbw_fail_msg(LB_EINVAL, "batch above 2^30");
     if (!dev_x || !dev_y) return lbw_fail_msg(LB_EINVAL, "NULL argument");
     const unsigned blocks = (unsigned)(((int64_t)B + kInferRows - 1) / kInferRows);
     hipLaunchKernelGGL(infer_kernel, dim3(blocks), dim3(kInferThreads), 0, h->stream, dev_x, B,

@@ -306,7 +306,8 @@ int check_all(const lb_wave_desc *descs, int n)
         if (st != LB_OK) return st;
         const long xsegs = (descs[i].nx + 63) / 64;
         tasks += xsegs * descs[i].ny * descs[i].nz;
-        if (tasks > INT32_MAX / 2) return fail(LB_EINVAL, "batch too large");
+        // a one-step launch runs 64 threads per task and a 1D grid holds fewer than 2^32
+        if (tasks > (long)(UINT32_MAX / 64)) return fail(LB_EINVAL, "batch too large");
     }
     return LB_OK;
 }
