@@ -115,7 +115,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
 {
     __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDK];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][LDK];
-    const int m_blk = blockIdx.y * TM, n_blk = blockIdx.x * TN;
+    // M (up to the batch) on x, whose grid dimension is the large one; N (<= 256) on y
+    const int m_blk = blockIdx.x * TM, n_blk = blockIdx.y * TN;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     // with a bias the sums start from it, as in the fused inference kernel, so that
@@ -216,18 +217,19 @@ __global__ void __launch_bounds__(256) loss_kernel(const float *y, const float *
 }
 
 // db[n] = sum_b delta[b, n] in two deterministic passes.  Pass 1: block
-// (cg, s) sums rows 256 s .. 256 s + 255 of columns 64 cg .. 64 cg + 63;
+// (s, cg) (chunk s on x, the long grid dimension) sums rows 256 s .. 256 s + 255
+// of columns 64 cg .. 64 cg + 63;
 // thread (c, g) takes rows g, g + 4, ... of column c, then the four row
 // groups are added in order.  Pass 2: partials added in chunk order.
 constexpr int kColRows = 256;
-constexpr int kMaxTrainBatch = 1 << 24;  // keeps the column-sum grid within 65536 rows of blocks
+constexpr int kMaxTrainBatch = 1 << 24;  // training batch limit (workspace about 11 KB per sample)
 __global__ void __launch_bounds__(256) colsum_part_kernel(const float *delta, int B, int N,
                                                           float *part)
 {
     __shared__ float red[4][64];
     const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int n = blockIdx.x * 64 + c;
-    const int b0 = blockIdx.y * kColRows;
+    const int n = blockIdx.y * 64 + c;
+    const int b0 = blockIdx.x * kColRows;
     const int b1 = min(b0 + kColRows, B);
     float s = 0.f;
     if (n < N)
@@ -235,7 +237,7 @@ __global__ void __launch_bounds__(256) colsum_part_kernel(const float *delta, in
     red[g][c] = s;
     __syncthreads();
     if (g == 0 && n < N)
-        part[(int64_t)blockIdx.y * N + n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+        part[(int64_t)blockIdx.x * N + n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
 }
 
 __global__ void colsum_final_kernel(const float *part, int n_chunks, int N, float *db)
@@ -528,7 +530,7 @@ namespace {
 
 void gemm(const lb_mlp *h, const GemmArgs &g)
 {
-    const dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM);
+    const dim3 grid((g.M + TM - 1) / TM, (g.N + TN - 1) / TN);
     hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, h->stream, g);
 }
 
@@ -596,7 +598,7 @@ void backward(const lb_mlp *h, const float *t, int B)
         g.ldo = K;
         gemm(h, g);
         const int n_chunks = (B + kColRows - 1) / kColRows;
-        hipLaunchKernelGGL(colsum_part_kernel, dim3((N + 63) / 64, n_chunks), dim3(256), 0,
+        hipLaunchKernelGGL(colsum_part_kernel, dim3(n_chunks, (N + 63) / 64), dim3(256), 0,
                            h->stream, h->at<float>(h->L.df[cur]), B, N, h->at<float>(h->L.part));
         hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 255) / 256), dim3(256), 0, h->stream,
                            h->at<float>(h->L.part), n_chunks, N,
