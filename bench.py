@@ -105,7 +105,7 @@ def get_variant(h):
 
 def kernel_name(storage, v):
     if v[3] == 2:
-        return "step2_kernel<{},rows={},nt={}>".format(storage, 2 if storage == "f64" else 4,
+        return "step2_kernel<{},rows={},nt={}>".format(storage, 4 if storage == "f32" else 2,
                                                        min(v[2], 1))
     return "step_kernel<3,{},{},{},{}>".format(storage, *v[:3])
 
