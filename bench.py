@@ -160,6 +160,14 @@ def surrogate_leg(stream, batch, steps=8000):
         net, log, train_s = S.MLP(max_batch=1024, seed=0), [(0, float("nan"))], 0.0
     te = S.table(json.load(open(test)))
     err = S.error_metric(net.predict(S.normalize(*te[:4])), te[4])
+    # share of queries the network hands to the LB: seeded draws over the whole input box
+    qrng = np.random.Generator(np.random.PCG64(2407))
+    nq = 100000
+    qkr = qrng.uniform(*S.BOX["kR"], nq)
+    qkh = qrng.uniform(*S.BOX["kh"], nq)
+    qra = qrng.uniform(*S.BOX["ratio"], nq)
+    qR = qrng.uniform(4.0, 16.0, nq)
+    fallback = float(1.0 - S.in_box(qkr, qkh, qra, qR).mean())
     x = torch.rand(batch, S.N_IN, device="cuda") * 2 - 1
     y = torch.empty(batch, device="cuda")
     for _ in range(3):
@@ -184,6 +192,11 @@ def surrogate_leg(stream, batch, steps=8000):
         "gain_over_batched_lb": round(batch / (ms * 1e-3) / (n_lb / lb_s), 1),
         "held_out_error": {k: (round(v, 5) if isinstance(v, float) else v)
                            for k, v in err.items()},
+        "fallback_fraction": {
+            "value": round(fallback, 4),
+            "queries": f"{nq} seeded draws (seed 2407), uniform over kR [0.05, 0.6], kh [0, pi/2], "
+                       "c_p/c0 [0.8, 1.5], R [4, 16] cells; those outside the trained box "
+                       "(kR < 2 pi 4/192) go to the LB"},
         "test_samples": len(te[0]), "train_samples": n_lb,
         "train_seconds": round(train_s, 2), "train_final_loss": log[-1][1],
         "lb_seconds_for_training_data": round(lb_s, 1),
