@@ -482,14 +482,6 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, const in
 constexpr int kZChunk = 32;
 constexpr int kTwoStepMaxPitch = 256;
 
-// A row (y, z) of a box (origin lo, extent n): -1 if the row misses it,
-// else the row's offset in cells.  Uniform over a wavefront.
-__device__ inline int box_row(const int *lo, const int *n, int y, int z)
-{
-    const int by = y - lo[1], bz = z - lo[2];
-    if (n[0] <= 0 || by < 0 || by >= n[1] || bz < 0 || bz >= n[2]) return -1;
-    return (bz * n[1] + by) * n[0];
-}
 
 template <typename C>
 __device__ inline void store_moments(gptr<C> mom, int mrow, int mb_lo0, int mb_n0, int x, C rho,
@@ -567,8 +559,9 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
     // neighbours within a plane, and the plane size; per plane only the z bases change
     const int64_t zstride = (int64_t)ny * pitch;
     int64_t yoff[R + 2], ymoff[R + 2], ynoff[R + 2];
-    // and the y part of the moment-box and sound-speed-box row indices (-1: row outside the box;
-    // box_row's index (bz n1 + by) n0 is the sum of a y part and a z part)
+    // and the y part of the moment-box and sound-speed-box row indices: a row (y, z) of a box
+    // (origin lo, extent n) starts at cell (bz n1 + by) n0, bz = z - lo2, by = y - lo1, the sum
+    // of a y part and a z part (-1: the row misses the box)
     int mb_y[R + 2], bb_y[R + 2];
 #pragma unroll
     for (int j = -1; j <= R; ++j) {
