@@ -152,6 +152,15 @@ def test_check_point_source_rules(P):
     assert arr[0].src_kind == 0
 
 
+def test_check_rejects_launches_beyond_32_bit_grids(P):
+    # 64 x 8192 x 8192 cells = 2^26 wave tasks of 64 threads: one thread more than a 1D grid holds
+    p = {"dim": 3, "nx": 64, "ny": 8192, "nz": 8192, "xbc": "periodic", "c0": 0.5, "radius": 0.0,
+         "center": (0, 0, 0), "rho_a": 1.0, "omega": 0.1}
+    assert P.check([p], "f16") == -1
+    p["nz"] = 8191                                   # 2^26 - 8192 tasks: within the limit
+    assert P.check([p], "f16") == 0
+
+
 def test_check_rejects_mixed_handles(P):
     arr, _ = P.make_descs([_sph(), _sph()], "f32")
     arr[1].storage = 2
