@@ -489,6 +489,9 @@ def main():
             "steps_per_launch": spl,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "one_step_equivalent_gbs": round(achieved * spl, 1),
+            # the same rate counted at 2 Q s bytes per cell update (steps_per_launch updates per
+            # cell per launch): above 1 when the launch keeps intermediate steps on chip
+            "per_update_frac": round(achieved * spl / HBM_PEAK_GBS, 4),
             "lattice_stage_only_ms": round(lattice_ms, 5),
             "lattice_stage_only_gbs": round(bytes_per_launch / (lattice_ms * 1e-3) / 1e9, 1),
             "copy_reference_gbs": round(copy_gbs, 1),
