@@ -219,9 +219,9 @@ int lb_wave_get_steps_per_launch(const lb_wave *h, int32_t *k);
 int lb_wave_set_graph(lb_wave *h, int32_t chunk);
 
 /* Plain device-to-device copy of `bytes` (multiple of 16, 16-byte aligned
- * pointers) on `hip_stream`, asynchronous.  A bandwidth reference for the
- * step kernel's roofline: it moves 2 * bytes through HBM with one read and
- * one write stream. */
+ * pointers) on `hip_stream`, asynchronous, with non-temporal loads and
+ * stores.  A bandwidth reference for the step kernel's roofline: it moves
+ * 2 * bytes through HBM with one read and one write stream. */
 int lb_stream_copy(const void *dev_src, void *dev_dst, size_t bytes, void *hip_stream);
 
 /* ---- empty-cavity calibration of the driven standing wave ---- */

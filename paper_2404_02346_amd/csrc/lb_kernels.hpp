@@ -989,21 +989,22 @@ __global__ void zero_kernel(uint4 *p, int64_t n16)
 
 // Plain copy (bandwidth reference for the roofline): each thread moves UNR
 // independent 16-byte words, consecutive threads consecutive words.
+using word16 = VecT<uint32_t, 4>::type;
 template <int UNR, bool NT>
-__global__ void __launch_bounds__(256) copy_kernel(const uint4 *__restrict__ src,
-                                                    uint4 *__restrict__ dst, int64_t n16)
+__global__ void __launch_bounds__(256) copy_kernel(const word16 *__restrict__ src,
+                                                    word16 *__restrict__ dst, int64_t n16)
 {
     const int64_t base = (int64_t)blockIdx.x * 256 * UNR + threadIdx.x;
-    uint4 v[UNR];
+    word16 v[UNR];
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
         const int64_t i = base + (int64_t)u * 256;
-        if (i < n16) v[u] = vload<uint4, NT>(src + i);
+        if (i < n16) v[u] = vload<word16, NT>(src + i);
     }
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
         const int64_t i = base + (int64_t)u * 256;
-        if (i < n16) vstore<uint4, NT>(dst + i, v[u]);
+        if (i < n16) vstore<word16, NT>(dst + i, v[u]);
     }
 }
 

@@ -1388,9 +1388,11 @@ int lb_stream_copy(const void *dev_src, void *dev_dst, size_t bytes, void *hip_s
     constexpr int UNR = 4;
     const int64_t blocks = (n16 + 256 * UNR - 1) / (256 * UNR);
     if (blocks > INT32_MAX) return fail(LB_EINVAL, "copy too large");
-    hipLaunchKernelGGL((copy_kernel<UNR, false>), dim3((unsigned)blocks), dim3(256), 0,
-                       static_cast<hipStream_t>(hip_stream), static_cast<const uint4 *>(dev_src),
-                       static_cast<uint4 *>(dev_dst), n16);
+    // non-temporal loads and stores: the fastest plain copy measured on this chip (6.2 TB/s
+    // against 5.75 with cached accesses, at 1.75 GiB each way)
+    hipLaunchKernelGGL((copy_kernel<UNR, true>), dim3((unsigned)blocks), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), static_cast<const word16 *>(dev_src),
+                       static_cast<word16 *>(dev_dst), n16);
     HIP_TRY(hipGetLastError());
     return LB_OK;
 }
