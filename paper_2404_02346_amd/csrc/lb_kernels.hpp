@@ -463,8 +463,9 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, const in
 // x = 64 (w % nw) + lane of row group w / nw, with nw = pitch / 64
 // wavefronts per row and 4 / nw row groups (with nw = 3 the fourth
 // wavefront idles but keeps the barriers).  A row group owns R consecutive
-// rows and a chunk of up to zchunk planes (chosen per handle: kZChunk, or
-// less when so few blocks would leave the chip idle).  It marches through
+// rows and a chunk of up to zchunk planes (chosen per handle: 64 with 4-row
+// groups, 32 with 2-row groups, or less when so few blocks would leave the
+// chip idle).  It marches through
 // the planes: for plane p it advances step t on its rows plus one halo row
 // on each side (of those only the population moving into the owned rows is
 // kept) and holds the post-collision values in registers; then it finishes
@@ -479,7 +480,6 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, const in
 // is bit-identical to that of two one-step launches.  Moments of f(t) and
 // f(t + 1) go to their moment boxes as in lattice_task.
 // ---------------------------------------------------------------------------
-constexpr int kZChunk = 32;
 constexpr int kTwoStepMaxPitch = 256;
 
 
