@@ -93,6 +93,32 @@ def test_two_step_graph_replay_and_stopping_instances(P):
         same(ref, run(P, probs, "f32", 2, 0, graph=graph, chunks=[37, 3, 40], trace=80))
 
 
+def test_two_step_longest_chunks_with_a_partial_chunk(P):
+    # 16 boxes of 96 x 128 x 256 give 1024 blocks with the longest FP32 plane chunk (64 planes), so
+    # the chunk is kept and the last one of every box is a partial chunk of 32 planes: the launch
+    # shape of the 16-sphere workload, plus a ragged end in z.  Two boxes start from seeded random
+    # states, the others from rest; 7 steps (the last one runs alone).
+    shape = (96, 128, 256)
+    probs = [problem(shape, R=6.0) for _ in range(16)]
+    ncell = shape[0] * shape[1] * shape[2]
+    seeded = {0: 91, 9: 92}
+    say("two-step, 16 boxes of 96 x 128 x 256, 64-plane chunks with a partial last chunk")
+    out = []
+    for spl in (1, 2):
+        h = P.LBWave(probs, storage="f32", trace_steps=8)
+        h.set_steps_per_launch(spl)
+        for i, seed in seeded.items():
+            h.set_state(i, workloads.random_state(seed, ncell, 7, scale=0.05))
+        h.step(7)
+        out.append(([h.get_state(i) for i in (0, 3, 9)], [h.trace(i, 7) for i in range(16)]))
+        h.close()
+    for x, y in zip(out[0][0], out[1][0]):
+        assert np.array_equal(x, y)
+    assert np.any(out[0][0][0] != 0) and np.any(out[0][0][1] != 0)
+    for x, y in zip(out[0][1], out[1][1]):
+        assert np.array_equal(x, y)
+
+
 def test_two_step_against_oracle_fp64(P, orc):
     p = problem((40, 16, 70), avg_start=5)
     n = 30
