@@ -580,10 +580,11 @@ int two_step_rows(int storage) { return storage == LB_F32 ? 4 : 2; }
 // 256 x 128 x 128, ms per launch with 64 / 32 / 16 planes: FP32 (4-row groups) 0.761 /
 // 0.796 / 0.791; FP16 (2-row groups) 0.490 / 0.484 / 0.498.
 int two_step_zchunk(int storage) { return storage == LB_F32 ? 64 : 32; }
-// Two-step plane chunks shrink (down to kMinZChunk) until a handle has this
-// many blocks: two rounds of the 512 that 256 CUs hold at two wavefronts per
-// SIMD (one round for FP64 at four).
-constexpr int64_t kMinBlocks2 = 1024;
+// Two-step plane chunks shrink (down to kMinZChunk) until a handle has at least as many blocks
+// as the chip holds at once: 512 for FP32 (256 CUs, two wavefronts per SIMD), 1024 for the
+// others (four).  One sphere of 256 x 128 x 128 in FP32: 2.25 forces/s with 512 blocks of 8
+// planes, 2.08 with 1024 of 4.
+int64_t two_step_min_blocks(int storage) { return storage == LB_F32 ? 512 : 1024; }
 constexpr int kMinZChunk = 4;
 
 // Prefetching the next plane's populations and sound speeds pays where the
@@ -1030,7 +1031,7 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
     }
     // two-step decomposition: row groups of R rows, 4 / nw groups per block,
     // chunks of zchunk planes: the longest chunk (fewest re-read halo planes)
-    // that still gives the chip about kMinBlocks2 blocks
+    // that still fills the chip (two_step_min_blocks)
     {
         const int R = two_step_rows(h->storage);
         auto blocks_for = [&](int zc, std::vector<int> *b0) {
@@ -1051,8 +1052,9 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
             return ok ? total : (int64_t)-1;
         };
         h->zchunk = two_step_zchunk(h->storage);
+        const int64_t min_blocks = two_step_min_blocks(h->storage);
         while (h->zchunk > kMinZChunk && blocks_for(h->zchunk, nullptr) >= 0 &&
-               blocks_for(h->zchunk, nullptr) < kMinBlocks2)
+               blocks_for(h->zchunk, nullptr) < min_blocks)
             h->zchunk /= 2;
         // (blocks_for also sizes blk0, which the segments below read in every case)
         const bool fits = blocks_for(h->zchunk, &h->blk0) >= 0 &&
