@@ -112,7 +112,9 @@ def kernel_name(storage, v):
 
 def measured_traffic(storage, variant):
     """HBM bytes per step-kernel launch from the committed counter summary, if current."""
-    path = os.path.join(ROOT, "profiles", "step2_kernel_sphere16_traffic.json")
+    name = ("step2_kernel_sphere16_traffic.json" if storage == "f32"
+            else f"step2_kernel_sphere16_{storage}_traffic.json")
+    path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as fh:
             d = json.load(fh)
