@@ -18,7 +18,9 @@
  * out layer by layer as W_l (out x in, row-major) followed by b_l; the
  * matrix products run on MFMA with BF16 operands (weights, activations and
  * back-propagated errors rounded to BF16) and FP32 accumulation; biases,
- * pre-activations, the loss and Adam are FP32, the loss sum FP64.
+ * pre-activations, the loss and Adam are FP32, the loss sum FP64.  Weight
+ * gradients are summed over the batch in fixed chunks and the chunk sums
+ * added in a fixed order, so gradients and training are deterministic.
  *
  * Conventions as in lb_wave.h: C linkage, lb_status return codes,
  * lb_last_error(), pointers are host pointers unless named dev_*, the caller
@@ -79,9 +81,19 @@ int lb_mlp_grad(lb_mlp *h, const float *dev_x, const float *dev_t, int32_t B, fl
                 double *host_loss);
 
 /* One Adam step on the mean squared error of the batch (asynchronous);
- * lb_mlp_last_loss() returns that batch's loss (synchronises). */
+ * lb_mlp_last_loss() returns that batch's loss (synchronises).  LB_EINVAL
+ * for a batch outside 1 .. max_batch, a NULL pointer, or hyper-parameters
+ * outside lr > 0, 0 <= beta < 1, eps > 0. */
 int lb_mlp_train_step(lb_mlp *h, const float *dev_x, const float *dev_t, int32_t B, float lr,
                       float beta1, float beta2, float eps);
+
+/* n_steps Adam steps on the same batch, step s with learning rate host_lr[s]
+ * (host array of n_steps floats, copied before return): the same kernels as
+ * n_steps calls of lb_mlp_train_step, enqueued from one call.  Asynchronous;
+ * every learning rate is checked before anything is enqueued. */
+int lb_mlp_train_steps(lb_mlp *h, const float *dev_x, const float *dev_t, int32_t B,
+                       int32_t n_steps, const float *host_lr, float beta1, float beta2,
+                       float eps);
 int lb_mlp_last_loss(lb_mlp *h, double *loss);
 
 /* One 16x16x32 BF16 MFMA tile D = A B (A 16 x 32, B 32 x 16, row-major BF16

@@ -91,183 +91,366 @@ __device__ inline float gelu_d(float z)
     return fmaf(z * 0.39894228040143268f, e, z >= 0.0f ? 1.0f - h : h);
 }
 
-enum Epi { EPI_BIAS_GELU = 0, EPI_BIAS = 1, EPI_STORE = 2, EPI_GELU_BWD = 3 };
+// ---------------------------------------------------------------------------
+// Training products.  Every product is C (M x N) = A (M x K) B (N x K)^T with
+// both operands stored K-contiguous (A row m at A + m s_am, B row n at B + n
+// s_bn), so a lane's MFMA fragment (8 consecutive k of one row) is one 16-byte
+// load straight into registers:
+//   forward  z_l     = a_l W_l^T          A = a_l (B x K_l),     B = W_l (N_l x K_l)
+//   errors   e_{l-1} = delta_l W_l        A = delta_l (B x N_l), B = W_l^T (K_l x N_l)
+//   weights  dW_l    = delta_l^T a_l      A = delta_l^T (N_l x B), B = a_l^T (K_l x B)
+// The forward and error epilogues therefore also write BF16 transposed copies
+// (batch-contiguous, rows padded with zeros to a multiple of 64 samples), and
+// the optimizer keeps a transposed BF16 mirror of every weight matrix.  The
+// weight products have K = batch (4096): K is split into at most kMaxSplit
+// chunks so that some 256 workgroups run, each chunk's sum goes to its own
+// slot, and finish_kernel adds the slots in chunk order (deterministic).
+// Bias gradients (column sums of the FP32 errors) and the loss are summed per
+// 64-sample block in the epilogues and finished the same way.
+// ---------------------------------------------------------------------------
 
-struct GemmArgs {
-    int M, N, K;
-    const uint16_t *A;  // A(m, k) = A[m * sam + k * sak]
-    int64_t sam, sak;
-    const uint16_t *B;  // B(k, n) = B[k * sbk + n * sbn]
-    int64_t sbk, sbn;
+enum Epi { EPI_FWD = 0, EPI_OUT = 1, EPI_DX = 2, EPI_PART = 3 };
+// operand storage: 16-byte BF16 vectors, or elementwise BF16 / FP32 with any strides
+enum OpMode { OP_VEC = 0, OP_BF16 = 1, OP_F32 = 2 };
+
+constexpr int kTile = 64;      // 64 x 64 output tile per workgroup, 4 wavefronts of 32 x 32
+constexpr int kStepsAhead = 8; // K steps of 32 whose fragments are loaded before use
+constexpr int kMaxSplit = 16;  // K chunks of a weight-gradient product
+constexpr int kMaxTrainBatch = 1 << 24;  // training batch limit (workspace about 14 KB per sample)
+
+struct GemmNT {
+    int M, N, K;       // K: true length (elementwise operands mask k >= K)
+    int Kp;            // K rounded up to 32: the loop bound (vector operands read zeros there)
+    int k_chunk;       // K range of chunk z: [z k_chunk, min(Kp, (z + 1) k_chunk))
+    int tiles_m, tiles_n, chunks;  // grid of this product: tile (mt, nt) of chunk z
+    const void *A;     // A(m, k) = A[m s_am + k s_ak]  (s_ak = 1 for OP_VEC)
+    int64_t s_am, s_ak;
+    const void *B;     // B(n, k) = B[n s_bn + k s_bk]  (s_bk = 1 for OP_VEC)
+    int64_t s_bn, s_bk;
     int epi;
-    const float *bias;   // N (EPI_BIAS_GELU, EPI_BIAS)
-    float *outf;         // FP32 output, row stride ldo
+    const float *bias;   // N (EPI_FWD, EPI_OUT)
+    float *outf;         // EPI_FWD: z (row stride ldo); EPI_OUT: y; EPI_PART: chunk z at outf + z M ldo
     int64_t ldo;
-    uint16_t *outb;      // BF16 output (EPI_BIAS_GELU, EPI_GELU_BWD), row stride ldo
-    const float *zprev;  // pre-activation for GELU' (EPI_GELU_BWD), row stride ldo
+    uint16_t *outb;      // BF16 row-major output (EPI_FWD: GELU(z); EPI_DX: error), may be NULL
+    uint16_t *outt;      // BF16 transposed output outt[n ldt + m] for m < m_pad (zero for m >= M)
+    int64_t ldt;
+    int m_pad;
+    const float *zprev;  // EPI_DX: pre-activation of the layer below (row stride ldo)
+    const float *target; // EPI_OUT: targets (training), or NULL (inference)
+    float inv_b2;        // EPI_OUT: 2 / batch
+    float *colpart;      // EPI_OUT (training), EPI_DX: per-64-row column sums [mt][N]
+    double *losspart;    // EPI_OUT (training): per-64-row sum of squared errors [mt]
 };
 
-constexpr int TM = 64, TN = 64, TK = 32, LDK = TK + 8;
-
-// C (M x N) = A (M x K) B (K x N), 64 x 64 per block, 4 wavefronts of 32 x 32
-// (2 x 2 MFMA tiles each), K in steps of 32 through LDS; then the epilogue.
-__global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g)
+template <int MODE>
+__device__ inline s16x8 load_frag(const void *base, int64_t s_row, int64_t s_k, int row, int nrows,
+                                  int k, int K)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t As[TM][LDK];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[TN][LDK];
-    // M (up to the batch) on x, whose grid dimension is the large one; N (<= 256) on y
-    const int m_blk = blockIdx.x * TM, n_blk = blockIdx.y * TN;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    s16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+    if (row >= nrows) return v;
+    if constexpr (MODE == OP_VEC) {
+        v = *reinterpret_cast<const s16x8 *>(static_cast<const uint16_t *>(base) +
+                                             (int64_t)row * s_row + k);
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            if (k + e < K) {
+                const int64_t o = (int64_t)row * s_row + (int64_t)(k + e) * s_k;
+                if constexpr (MODE == OP_BF16)
+                    v[e] = (short)static_cast<const uint16_t *>(base)[o];
+                else
+                    v[e] = (short)to_bf16(static_cast<const float *>(base)[o]);
+            }
+        }
+    }
+    return v;
+}
+
+// one 64 x 64 output tile (mt, nt) of K chunk kz
+template <int AM, int BM>
+__device__ inline void gemm_tile(const GemmNT &g, int mt, int nt, int kz, float (*red)[kTile],
+                                 double *lred)
+{
+    const int m_blk = mt * kTile, n_blk = nt * kTile;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int wm = w >> 1, wn = w & 1;
+    const int kl = 8 * (lane >> 4);
+    const int k_beg = kz * g.k_chunk;
+    const int k_end = min(g.Kp, k_beg + g.k_chunk);
+    int ra[2], rb[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        ra[i] = m_blk + wm * 32 + i * 16 + (lane & 15);
+        rb[i] = n_blk + wn * 32 + i * 16 + (lane & 15);
+    }
+    // lane holds column rb[j], rows mrow + 16 i + v (v = 0..3) of the result
+    const int mrow = m_blk + wm * 32 + 4 * (lane >> 4);
     // with a bias the sums start from it, as in the fused inference kernel, so that
     // both forwards round every activation identically
-    const bool has_bias = g.epi == EPI_BIAS_GELU || g.epi == EPI_BIAS;
+    const bool has_bias = g.epi == EPI_FWD || g.epi == EPI_OUT;
     f32x4 acc[2][2];
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-        const int n = n_blk + wn * 32 + j * 16 + (lane & 15);
-        const float b0 = (has_bias && n < g.N) ? g.bias[n] : 0.f;
+        const float b0 = (has_bias && rb[j] < g.N) ? g.bias[rb[j]] : 0.f;
 #pragma unroll
         for (int i = 0; i < 2; ++i) acc[i][j] = f32x4{b0, b0, b0, b0};
     }
+    // the epilogue's other inputs are fetched before the product, so that their
+    // latency overlaps it: z of the layer below (EPI_DX), the targets (EPI_OUT)
+    float pre[2][2][4];
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = mrow + 16 * i + v;
+                float q = 0.f;
+                if (g.epi == EPI_DX && m < g.M && rb[j] < g.N) q = g.zprev[(int64_t)m * g.ldo + rb[j]];
+                if (g.epi == EPI_OUT && g.target && j == 0 && m < g.M) q = g.target[m];
+                pre[j][i][v] = q;
+            }
 
-    for (int k0 = 0; k0 < g.K; k0 += TK) {
+    for (int kb = k_beg; kb < k_end; kb += 32 * kStepsAhead) {
+        s16x8 a[kStepsAhead][2], b[kStepsAhead][2];
 #pragma unroll
-        for (int e = 0; e < (TM * TK) / 256; ++e) {
-            const int idx = tid + 256 * e;
-            const int r = idx >> 5, kk = idx & 31;
-            const int k = k0 + kk;
-            const int m = m_blk + r, n = n_blk + r;
-            As[r][kk] = (m < g.M && k < g.K) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : 0;
-            Bs[r][kk] = (n < g.N && k < g.K) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : 0;
-        }
-        __syncthreads();
-        const int kk = 8 * (lane >> 4);
-        bf16x8 af[2], bfr[2];
+        for (int s = 0; s < kStepsAhead; ++s) {
+            const int k = kb + 32 * s;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int row = wm * 32 + i * 16 + (lane & 15);
-            af[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s16x8 *>(&As[row][kk]));
+            for (int i = 0; i < 2; ++i) {
+                a[s][i] = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                b[s][i] = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            }
+            if (k < k_end) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    a[s][i] = load_frag<AM>(g.A, g.s_am, g.s_ak, ra[i], g.M, k + kl, g.K);
+                    b[s][i] = load_frag<BM>(g.B, g.s_bn, g.s_bk, rb[i], g.N, k + kl, g.K);
+                }
+            }
         }
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int col = wn * 32 + j * 16 + (lane & 15);
-            bfr[j] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s16x8 *>(&Bs[col][kk]));
+        for (int s = 0; s < kStepsAhead; ++s) {
+            if (kb + 32 * s < k_end) {
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            __builtin_bit_cast(bf16x8, a[s][i]), __builtin_bit_cast(bf16x8, b[s][j]),
+                            acc[i][j], 0, 0, 0);
+            }
         }
+    }
+
+    if (g.epi == EPI_PART) {
+        float *o = g.outf + (int64_t)kz * g.M * g.ldo;
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-        __syncthreads();
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = mrow + 16 * i + v;
+                    if (m < g.M && rb[j] < g.N) o[(int64_t)m * g.ldo + rb[j]] = acc[i][j][v];
+                }
+        return;
     }
+    float csum[2] = {0.f, 0.f};
+    double lsum = 0.0;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+        const int n = rb[j];
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int i = 0; i < 2; ++i) {
+            float tv[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int m = m_blk + wm * 32 + i * 16 + 4 * (lane >> 4) + v;
-                const int n = n_blk + wn * 32 + j * 16 + (lane & 15);
-                if (m >= g.M || n >= g.N) continue;
+                const int m = mrow + 16 * i + v;
+                const bool ok = m < g.M && n < g.N;
                 const float c = acc[i][j][v];
                 const int64_t o = (int64_t)m * g.ldo + n;
-                switch (g.epi) {
-                case EPI_BIAS_GELU:
-                    g.outf[o] = c;
-                    g.outb[o] = to_bf16(gelu(c));
-                    break;
-                case EPI_BIAS: g.outf[o] = c; break;
-                case EPI_STORE: g.outf[o] = c; break;
-                default: {
-                    const float d = c * gelu_d(g.zprev[o]);
-                    g.outf[o] = d;
-                    g.outb[o] = to_bf16(d);
+                float t = 0.f;
+                if (g.epi == EPI_FWD) {
+                    if (ok) {
+                        t = gelu(c);
+                        g.outf[o] = c;
+                        g.outb[o] = to_bf16(t);
+                    }
+                } else if (g.epi == EPI_OUT) {
+                    if (ok) {
+                        g.outf[m] = c;
+                        if (g.target) {
+                            const float e = c - pre[0][i][v];
+                            t = e * g.inv_b2;
+                            lsum += (double)e * (double)e;
+                            csum[j] += t;
+                        }
+                    }
+                } else {  // EPI_DX
+                    if (ok) {
+                        t = c * gelu_d(pre[j][i][v]);
+                        if (g.outb) g.outb[o] = to_bf16(t);
+                        csum[j] += t;
+                    }
                 }
-                }
+                tv[v] = t;
             }
-}
-
-__global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) y[i] = to_bf16(x[i]);
-}
-
-// delta = 2 (y - t) / B (FP32 and BF16), loss = sum (y - t)^2 / B in FP64 (one block)
-__global__ void __launch_bounds__(256) loss_kernel(const float *y, const float *t, int B,
-                                                   float *df, uint16_t *db, double *loss)
-{
-    __shared__ double red[256];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < B; b += 256) {
-        const float e = y[b] - t[b];
-        const float d = 2.0f * e / (float)B;
-        df[b] = d;
-        db[b] = to_bf16(d);
-        s += (double)e * (double)e;
+            const int m0 = mrow + 16 * i;
+            if (g.outt && n < g.N && m0 < g.m_pad) {
+                const uint32_t lo = to_bf16x2(tv[0], tv[1]), hi = to_bf16x2(tv[2], tv[3]);
+                *reinterpret_cast<uint2 *>(g.outt + (int64_t)n * g.ldt + m0) = make_uint2(lo, hi);
+            }
+        }
     }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if (g.colpart) {
+        // column sums over this block's 64 rows: a lane's 8 rows in order, then the four
+        // lane groups of a column (butterfly), then the two wavefront rows
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            float s = csum[j];
+            s += __shfl_xor(s, 16);
+            s += __shfl_xor(s, 32);
+            if (lane < 16) red[wm][wn * 32 + j * 16 + lane] = s;
+        }
+        if (g.losspart) {
+            lsum += __shfl_xor(lsum, 16);
+            lsum += __shfl_xor(lsum, 32);
+            if (wn == 0 && lane == 0) lred[wm] = lsum;
+        }
         __syncthreads();
+        if (threadIdx.x < kTile) {
+            const int n = n_blk + threadIdx.x;
+            if (n < g.N)
+                g.colpart[(int64_t)mt * g.N + n] = red[0][threadIdx.x] + red[1][threadIdx.x];
+        }
+        if (g.losspart && threadIdx.x == 0) g.losspart[mt] = lred[0] + lred[1];
     }
-    if (threadIdx.x == 0) *loss = red[0] / (double)B;
 }
 
-// db[n] = sum_b delta[b, n] in two deterministic passes.  Pass 1: block
-// (s, cg) (chunk s on x, the long grid dimension) sums rows 256 s .. 256 s + 255
-// of columns 64 cg .. 64 cg + 63;
-// thread (c, g) takes rows g, g + 4, ... of column c, then the four row
-// groups are added in order.  Pass 2: partials added in chunk order.
-constexpr int kColRows = 256;
-constexpr int kMaxTrainBatch = 1 << 24;  // training batch limit (workspace about 11 KB per sample)
-__global__ void __launch_bounds__(256) colsum_part_kernel(const float *delta, int B, int N,
-                                                          float *part)
+// One launch runs two independent products: blocks [0, n0) take tiles of g0, the
+// rest tiles of g1 (a single product passes n0 = its block count).  Block b of a
+// product is tile (b mod tiles_m, (b / tiles_m) mod tiles_n) of chunk
+// b / (tiles_m tiles_n).
+template <int AM0, int BM0, int AM1, int BM1>
+__global__ void __launch_bounds__(256) gemm_nt_kernel(GemmNT g0, GemmNT g1, int n0)
 {
-    __shared__ float red[4][64];
-    const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const int n = blockIdx.y * 64 + c;
-    const int b0 = blockIdx.x * kColRows;
-    const int b1 = min(b0 + kColRows, B);
-    float s = 0.f;
-    if (n < N)
-        for (int b = b0 + g; b < b1; b += 4) s += delta[(int64_t)b * N + n];
-    red[g][c] = s;
-    __syncthreads();
-    if (g == 0 && n < N)
-        part[(int64_t)blockIdx.x * N + n] = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
+    __shared__ float red[2][kTile];
+    __shared__ double lred[2];
+    const int b = blockIdx.x;
+    if (b < n0) {
+        gemm_tile<AM0, BM0>(g0, b % g0.tiles_m, (b / g0.tiles_m) % g0.tiles_n,
+                            b / (g0.tiles_m * g0.tiles_n), red, lred);
+    } else {
+        const int c = b - n0;
+        gemm_tile<AM1, BM1>(g1, c % g1.tiles_m, (c / g1.tiles_m) % g1.tiles_n,
+                            c / (g1.tiles_m * g1.tiles_n), red, lred);
+    }
 }
 
-__global__ void colsum_final_kernel(const float *part, int n_chunks, int N, float *db)
-{
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    float s = 0.f;
-    for (int k = 0; k < n_chunks; ++k) s += part[(int64_t)k * N + n];
-    db[n] = s;
-}
+struct FinishArgs {
+    float *p, *g, *m, *v;
+    uint16_t *pb, *pbT;
+    const float *wpart[kLayers];  // chunk sums of dW_l: [chunk][N_l][K_l]
+    int wsplit[kLayers];
+    const float *bpart[kLayers];  // block sums of db_l: [block][N_l]
+    int nblk;
+    const double *losspart;
+    double *loss;
+    int B;
+    int adam;
+    float lr, b1, b2, eps, c1, c2;
+};
 
-__global__ void adam_kernel(float *p, const float *g, float *m, float *v, uint16_t *pb, int n,
-                            float lr, float b1, float b2, float eps, float c1, float c2)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
-    p[i] = pi;
-    pb[i] = to_bf16(pi);
-}
-
-__global__ void mirror_kernel(const float *p, uint16_t *pb, int n)
+// gradient of every parameter from its partial sums (chunk or block order), the
+// loss, and (adam != 0) one Adam step with the BF16 mirrors W and W^T refreshed
+__global__ void __launch_bounds__(256) finish_kernel(FinishArgs f)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) pb[i] = to_bf16(p[i]);
+    if (i == 0) {
+        double s = 0.0;
+        for (int b0 = 0; b0 < f.nblk; b0 += 16) {
+            double q[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) q[u] = b0 + u < f.nblk ? f.losspart[b0 + u] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (b0 + u < f.nblk) s += q[u];
+        }
+        *f.loss = s / (double)f.B;
+    }
+    if (i >= kParams) return;
+    int l = 0;
+#pragma unroll
+    for (int q = 1; q < kLayers; ++q)
+        if (i >= param_offset_w(q)) l = q;
+    int K = kDims[0], N = kDims[1], S = f.wsplit[0];
+    const float *wp = f.wpart[0], *bp = f.bpart[0];
+#pragma unroll
+    for (int q = 1; q < kLayers; ++q)
+        if (l == q) {
+            K = kDims[q];
+            N = kDims[q + 1];
+            S = f.wsplit[q];
+            wp = f.wpart[q];
+            bp = f.bpart[q];
+        }
+    const int local = i - param_offset_w(l);
+    const bool weight = local < N * K;
+    // every partial is loaded before the first add (a runtime-length loop would wait
+    // for each load in turn); the sums still run in chunk or block order
+    float gi = 0.f;
+    if (weight) {
+        float q[kMaxSplit];
+#pragma unroll
+        for (int s = 0; s < kMaxSplit; ++s) q[s] = s < S ? wp[(int64_t)s * N * K + local] : 0.f;
+#pragma unroll
+        for (int s = 0; s < kMaxSplit; ++s)
+            if (s < S) gi += q[s];
+    } else {
+        const int n = local - N * K;
+        for (int b0 = 0; b0 < f.nblk; b0 += 16) {
+            float q[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) q[u] = b0 + u < f.nblk ? bp[(int64_t)(b0 + u) * N + n] : 0.f;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (b0 + u < f.nblk) gi += q[u];
+        }
+    }
+    f.g[i] = gi;
+    if (!f.adam) return;
+    const float mi = f.b1 * f.m[i] + (1.f - f.b1) * gi;
+    const float vi = f.b2 * f.v[i] + (1.f - f.b2) * gi * gi;
+    f.m[i] = mi;
+    f.v[i] = vi;
+    const float pi = f.p[i] - f.lr * (mi / f.c1) / (sqrtf(vi / f.c2) + f.eps);
+    f.p[i] = pi;
+    const uint16_t pbi = to_bf16(pi);
+    f.pb[i] = pbi;
+    if (weight) f.pbT[param_offset_w(l) + (local % K) * N + local / K] = pbi;
+}
+
+// BF16 mirrors W and W^T of the FP32 parameters (after they are set)
+__global__ void mirror_kernel(const float *p, uint16_t *pb, uint16_t *pbT)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kParams) return;
+    const uint16_t b = to_bf16(p[i]);
+    pb[i] = b;
+    int l = 0;
+#pragma unroll
+    for (int q = 1; q < kLayers; ++q)
+        if (i >= param_offset_w(q)) l = q;
+    int K = kDims[0], N = kDims[1];
+#pragma unroll
+    for (int q = 1; q < kLayers; ++q)
+        if (l == q) {
+            K = kDims[q];
+            N = kDims[q + 1];
+        }
+    const int local = i - param_offset_w(l);
+    if (local < N * K) pbT[param_offset_w(l) + (local % K) * N + local / K] = b;
 }
 
 __global__ void zero_f32_kernel(float *p, int64_t n)
@@ -464,17 +647,22 @@ __global__ void __launch_bounds__(kInferThreads, kInferWaves / 2)
 
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+inline int round_up(int v, int q) { return (v + q - 1) / q * q; }
 
 struct Layout {
-    size_t p, g, m, v, pb;           // parameters, gradients, Adam moments, BF16 mirror
-    size_t xb;                       // BF16 input (B x kIn)
-    size_t act[kLayers];             // BF16 activations a_1..a_4 (B x 256); act[0] unused
+    size_t p, g, m, v, pb, pbT;      // parameters, gradients, Adam moments, BF16 mirrors W and W^T
+    size_t act[kLayers];             // BF16 activations a_1..a_4, row-major (B x 256); act[0] unused
+    size_t actT[kLayers];            // the same transposed (256 x ldt)
     size_t z[kLayers];               // FP32 pre-activations z_0..z_3 (B x 256)
     size_t y;                        // FP32 output (B)
-    size_t df[2], dbf[2];            // FP32 / BF16 errors, ping-pong (B x 256)
-    size_t part;                     // FP32 column-sum partials (ceil(B / 256) x 256)
+    size_t drm[2], dT[2];            // BF16 errors of the hidden layers, row-major and transposed
+    size_t d4;                       // BF16 error of the output layer (ldt)
+    size_t wpart[kLayers];           // FP32 chunk sums of the weight gradients
+    size_t bpart[kLayers];           // FP32 block sums of the bias gradients
+    size_t lpart;                    // FP64 block sums of the squared errors
     size_t loss;                     // FP64
     size_t total;
+    int64_t ldt;                     // row stride of the transposed copies (max batch padded to 64)
 };
 
 Layout plan(int Bm)
@@ -486,22 +674,32 @@ Layout plan(int Bm)
         off = align_up(off + bytes);
         return o;
     };
+    const size_t Bp = (size_t)round_up(Bm, kTile);
+    const size_t nblk = Bp / kTile;
+    L.ldt = (int64_t)Bp;
     L.p = take(4 * (size_t)kParams);
     L.g = take(4 * (size_t)kParams);
     L.m = take(4 * (size_t)kParams);
     L.v = take(4 * (size_t)kParams);
     L.pb = take(2 * (size_t)kParams);
-    L.xb = take(2 * kIn * (size_t)Bm);
+    L.pbT = take(2 * (size_t)kParams);
     for (int l = 0; l < kLayers; ++l) {
         L.act[l] = take(2 * (size_t)kHidden * Bm);
+        L.actT[l] = take(2 * (size_t)kHidden * Bp);
         L.z[l] = take(4 * (size_t)kHidden * Bm);
     }
     L.y = take(4 * (size_t)Bm);
     for (int i = 0; i < 2; ++i) {
-        L.df[i] = take(4 * (size_t)kHidden * Bm);
-        L.dbf[i] = take(2 * (size_t)kHidden * Bm);
+        L.drm[i] = take(2 * (size_t)kHidden * Bm);
+        L.dT[i] = take(2 * (size_t)kHidden * Bp);
     }
-    L.part = take(4 * (size_t)kHidden * (((size_t)Bm + kColRows - 1) / kColRows));
+    L.d4 = take(2 * Bp);
+    for (int l = 0; l < kLayers; ++l) {
+        const size_t nk = (size_t)kDims[l + 1] * kDims[l];
+        L.wpart[l] = take(4 * nk * kMaxSplit);
+        L.bpart[l] = take(4 * (size_t)kDims[l + 1] * nblk);
+    }
+    L.lpart = take(8 * nblk);
     L.loss = take(8);
     L.total = off;
     return L;
@@ -528,101 +726,203 @@ namespace {
         if (e_ != hipSuccess) return lbw_fail_msg(LB_EDEVICE, hipGetErrorString(e_));   \
     } while (0)
 
-void gemm(const lb_mlp *h, const GemmArgs &g)
+GemmNT base_args()
 {
-    const dim3 grid((g.M + TM - 1) / TM, (g.N + TN - 1) / TN);
-    hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, h->stream, g);
+    GemmNT g;
+    std::memset(&g, 0, sizeof g);
+    return g;
 }
 
-GemmArgs base_args() { GemmArgs g; std::memset(&g, 0, sizeof g); return g; }
-
-// forward for B samples; keeps activations and pre-activations for backward
-void forward(const lb_mlp *h, const float *x, int B, float *y)
+// K split into chunks of whole 32-steps: at most `want` chunks, equal but the last
+int split_chunks(int steps, int want, int *per_out = nullptr)
 {
-    const int64_t nx = kIn * (int64_t)B;
-    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, h->stream,
-                       x, h->at<uint16_t>(h->L.xb), nx);
-    const uint16_t *a = h->at<uint16_t>(h->L.xb);
+    want = std::max(1, std::min(want, steps));
+    const int per = (steps + want - 1) / want;
+    if (per_out) *per_out = per;
+    return (steps + per - 1) / per;
+}
+
+// the grid of one product: ceil(M/64) x ceil(N/64) tiles, split_chunks(., want) K chunks
+void plan_gemm(GemmNT &g, int want)
+{
+    g.Kp = round_up(g.K, 32);
+    int per = 0;
+    g.chunks = split_chunks(g.Kp / 32, want, &per);
+    g.k_chunk = 32 * per;
+    g.tiles_m = (g.M + kTile - 1) / kTile;
+    g.tiles_n = (g.N + kTile - 1) / kTile;
+}
+
+int blocks_of(const GemmNT &g) { return g.tiles_m * g.tiles_n * g.chunks; }
+
+// one product C = A B^T in one launch
+template <int AM, int BM>
+void gemm(const lb_mlp *h, GemmNT g, int want = 1)
+{
+    plan_gemm(g, want);
+    const int n = blocks_of(g);
+    hipLaunchKernelGGL((gemm_nt_kernel<AM, BM, AM, BM>), dim3(n), dim3(256), 0, h->stream, g, g, n);
+}
+
+// two independent products in one launch
+template <int AM0, int BM0, int AM1, int BM1>
+void gemm2(const lb_mlp *h, GemmNT g0, int want0, GemmNT g1, int want1)
+{
+    plan_gemm(g0, want0);
+    plan_gemm(g1, want1);
+    const int n0 = blocks_of(g0), n1 = blocks_of(g1);
+    hipLaunchKernelGGL((gemm_nt_kernel<AM0, BM0, AM1, BM1>), dim3(n0 + n1), dim3(256), 0,
+                       h->stream, g0, g1, n0);
+}
+
+// requested K chunks of a weight-gradient product: about 256 workgroups in all,
+// each chunk at least 4 steps of 32, at most kMaxSplit chunks
+int weight_split(int l, int B)
+{
+    const int tiles = ((kDims[l + 1] + kTile - 1) / kTile) * ((kDims[l] + kTile - 1) / kTile);
+    const int steps = round_up(B, 32) / 32;
+    const int want = std::min(kMaxSplit, std::max(1, 256 / tiles));
+    return std::max(1, std::min(want, steps / 4));
+}
+
+// forward for B samples; keeps activations (both layouts) and pre-activations for
+// the backward pass.  With targets t the output layer also forms the output error
+// 2 (y - t) / B, its block sums and the blocks' squared errors.
+void forward(const lb_mlp *h, const float *x, int B, float *y, const float *t)
+{
+    const Layout &L = h->L;
+    const int m_pad = round_up(B, kTile);
     for (int l = 0; l < kLayers; ++l) {
         const int K = kDims[l], N = kDims[l + 1];
-        GemmArgs g = base_args();
+        GemmNT g = base_args();
         g.M = B;
         g.N = N;
         g.K = K;
-        g.A = a;
-        g.sam = K;
-        g.sak = 1;
-        g.B = h->at<uint16_t>(h->L.pb) + param_offset_w(l);  // B(k, n) = W[n][k]
-        g.sbk = 1;
-        g.sbn = K;
-        g.bias = h->at<float>(h->L.p) + param_offset_b(l);
+        g.B = h->at<uint16_t>(L.pb) + param_offset_w(l);  // W_l (N x K)
+        g.s_bn = K;
+        g.s_bk = 1;
+        g.bias = h->at<float>(L.p) + param_offset_b(l);
         g.ldo = N;
+        g.ldt = L.ldt;
+        g.m_pad = m_pad;
         if (l < kLayers - 1) {
-            g.epi = EPI_BIAS_GELU;
-            g.outf = h->at<float>(h->L.z[l]);
-            g.outb = h->at<uint16_t>(h->L.act[l + 1]);
-            a = g.outb;
+            g.epi = EPI_FWD;
+            g.outf = h->at<float>(L.z[l]);
+            g.outb = h->at<uint16_t>(L.act[l + 1]);
+            g.outt = h->at<uint16_t>(L.actT[l + 1]);
         } else {
-            g.epi = EPI_BIAS;
+            g.epi = EPI_OUT;
             g.outf = y;
+            if (t) {
+                g.target = t;
+                g.inv_b2 = 2.0f / (float)B;
+                g.outt = h->at<uint16_t>(L.d4);
+                g.colpart = h->at<float>(L.bpart[l]);
+                g.losspart = h->at<double>(L.lpart);
+            }
         }
-        gemm(h, g);
+        if (l == 0) {
+            g.A = x;  // FP32 input, converted to BF16 on load
+            g.s_am = K;
+            g.s_ak = 1;
+            gemm<OP_F32, OP_BF16>(h, g);
+        } else {
+            g.A = h->at<uint16_t>(L.act[l]);
+            g.s_am = K;
+            g.s_ak = 1;
+            gemm<OP_VEC, OP_VEC>(h, g);
+        }
     }
 }
 
-// loss, gradients of every parameter into L.g
-void backward(const lb_mlp *h, const float *t, int B)
+// weight gradients (chunk sums) of every layer and block sums of the errors.  The
+// weight gradient of layer l and the error of layer l - 1 both read only layer
+// l's error, so they share one launch.
+void backward(const lb_mlp *h, const float *x, int B)
 {
-    float *y = h->at<float>(h->L.y);
+    const Layout &L = h->L;
+    const int m_pad = round_up(B, kTile);
     int cur = 0;
-    hipLaunchKernelGGL(loss_kernel, dim3(1), dim3(256), 0, h->stream, y, t, B,
-                       h->at<float>(h->L.df[cur]), h->at<uint16_t>(h->L.dbf[cur]),
-                       h->at<double>(h->L.loss));
     for (int l = kLayers - 1; l >= 0; --l) {
         const int K = kDims[l], N = kDims[l + 1];
-        const uint16_t *a_in = (l == 0) ? h->at<uint16_t>(h->L.xb) : h->at<uint16_t>(h->L.act[l]);
-        const uint16_t *dl = h->at<uint16_t>(h->L.dbf[cur]);
-        // dW_l (N x K) = delta_l^T (N x B) a_l (B x K)
-        GemmArgs g = base_args();
+        // this layer's error: transposed (N x ldt) and row-major (B x N)
+        const uint16_t *eT = (l == kLayers - 1) ? h->at<uint16_t>(L.d4) : h->at<uint16_t>(L.dT[cur]);
+        const uint16_t *erm = (l == kLayers - 1) ? h->at<uint16_t>(L.d4) : h->at<uint16_t>(L.drm[cur]);
+        // dW_l (N x K) = delta_l^T a_l
+        GemmNT g = base_args();
         g.M = N;
         g.N = K;
         g.K = B;
-        g.A = dl;
-        g.sam = 1;
-        g.sak = N;
-        g.B = a_in;
-        g.sbk = K;
-        g.sbn = 1;
-        g.epi = EPI_STORE;
-        g.outf = h->at<float>(h->L.g) + param_offset_w(l);
+        g.A = eT;
+        g.s_am = L.ldt;
+        g.s_ak = 1;
+        g.epi = EPI_PART;
+        g.outf = h->at<float>(L.wpart[l]);
         g.ldo = K;
-        gemm(h, g);
-        const int n_chunks = (B + kColRows - 1) / kColRows;
-        hipLaunchKernelGGL(colsum_part_kernel, dim3(n_chunks, (N + 63) / 64), dim3(256), 0,
-                           h->stream, h->at<float>(h->L.df[cur]), B, N, h->at<float>(h->L.part));
-        hipLaunchKernelGGL(colsum_final_kernel, dim3((N + 255) / 256), dim3(256), 0, h->stream,
-                           h->at<float>(h->L.part), n_chunks, N,
-                           h->at<float>(h->L.g) + param_offset_b(l));
-        if (l == 0) break;
-        // delta_{l-1} (B x K) = (delta_l (B x N) W_l (N x K)) * gelu'(z_{l-1})
-        GemmArgs d = base_args();
+        const int split = weight_split(l, B);
+        if (l == 0) {
+            g.B = x;  // FP32 input: B(n, k) = x[k][n]
+            g.s_bn = 1;
+            g.s_bk = kIn;
+            gemm<OP_VEC, OP_F32>(h, g, split);
+            break;
+        }
+        g.B = h->at<uint16_t>(L.actT[l]);
+        g.s_bn = L.ldt;
+        g.s_bk = 1;
+        // delta_{l-1} (B x K) = (delta_l W_l) * gelu'(z_{l-1}), with its block column sums
+        GemmNT d = base_args();
         d.M = B;
         d.N = K;
         d.K = N;
-        d.A = dl;
-        d.sam = N;
-        d.sak = 1;
-        d.B = h->at<uint16_t>(h->L.pb) + param_offset_w(l);  // B(k, n) = W[k][n]
-        d.sbk = K;
-        d.sbn = 1;
-        d.epi = EPI_GELU_BWD;
-        d.zprev = h->at<float>(h->L.z[l - 1]);
-        d.outf = h->at<float>(h->L.df[1 - cur]);
-        d.outb = h->at<uint16_t>(h->L.dbf[1 - cur]);
+        d.A = erm;
+        d.s_am = N;
+        d.s_ak = 1;
+        d.B = h->at<uint16_t>(L.pbT) + param_offset_w(l);  // W_l^T (K x N)
+        d.s_bn = N;
+        d.s_bk = 1;
+        d.epi = EPI_DX;
+        d.zprev = h->at<float>(L.z[l - 1]);
         d.ldo = K;
-        gemm(h, d);
+        d.outb = (l > 1) ? h->at<uint16_t>(L.drm[1 - cur]) : nullptr;
+        d.outt = h->at<uint16_t>(L.dT[1 - cur]);
+        d.ldt = L.ldt;
+        d.m_pad = m_pad;
+        d.colpart = h->at<float>(L.bpart[l - 1]);
+        if (N < 32)
+            gemm2<OP_VEC, OP_VEC, OP_BF16, OP_BF16>(h, g, split, d, 1);  // the output layer's K = 1
+        else
+            gemm2<OP_VEC, OP_VEC, OP_VEC, OP_VEC>(h, g, split, d, 1);
         cur = 1 - cur;
     }
+}
+
+FinishArgs finish_args(const lb_mlp *h, int B)
+{
+    const Layout &L = h->L;
+    FinishArgs f;
+    std::memset(&f, 0, sizeof f);
+    f.p = h->at<float>(L.p);
+    f.g = h->at<float>(L.g);
+    f.m = h->at<float>(L.m);
+    f.v = h->at<float>(L.v);
+    f.pb = h->at<uint16_t>(L.pb);
+    f.pbT = h->at<uint16_t>(L.pbT);
+    for (int l = 0; l < kLayers; ++l) {
+        f.wpart[l] = h->at<float>(L.wpart[l]);
+        f.wsplit[l] = split_chunks(round_up(B, 32) / 32, weight_split(l, B));
+        f.bpart[l] = h->at<float>(L.bpart[l]);
+    }
+    f.nblk = round_up(B, kTile) / kTile;
+    f.losspart = h->at<double>(L.lpart);
+    f.loss = h->at<double>(L.loss);
+    f.B = B;
+    return f;
+}
+
+void finish(const lb_mlp *h, const FinishArgs &f)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3((kParams + 255) / 256), dim3(256), 0, h->stream, f);
 }
 
 int check_batch(const lb_mlp *h, int B)
@@ -630,6 +930,31 @@ int check_batch(const lb_mlp *h, int B)
     if (!h) return lbw_fail_msg(LB_EINVAL, "handle is NULL");
     if (B < 1 || B > h->Bm) return lbw_fail_msg(LB_EINVAL, "batch outside 1 .. max_batch");
     return LB_OK;
+}
+
+int check_adam(float lr, float beta1, float beta2, float eps)
+{
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return lbw_fail_msg(LB_EINVAL, "bad Adam hyper-parameters");
+    return LB_OK;
+}
+
+// one Adam step (the caller has checked the arguments)
+void adam_step(lb_mlp *h, const float *x, const float *t, int B, float lr, float beta1,
+               float beta2, float eps)
+{
+    forward(h, x, B, h->at<float>(h->L.y), t);
+    backward(h, x, B);
+    h->step++;
+    FinishArgs f = finish_args(h, B);
+    f.adam = 1;
+    f.lr = lr;
+    f.b1 = beta1;
+    f.b2 = beta2;
+    f.eps = eps;
+    f.c1 = 1.f - std::pow(beta1, (float)h->step);
+    f.c2 = 1.f - std::pow(beta2, (float)h->step);
+    finish(h, f);
 }
 
 }  // namespace
@@ -664,7 +989,7 @@ int lb_mlp_create(int32_t max_batch, void *dev_workspace, size_t workspace_bytes
     hipLaunchKernelGGL(zero_f32_kernel, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, h->stream,
                        h->at<float>(L.p), nz);
     hipLaunchKernelGGL(mirror_kernel, dim3((kParams + 255) / 256), dim3(256), 0, h->stream,
-                       h->at<float>(L.p), h->at<uint16_t>(L.pb), kParams);
+                       h->at<float>(L.p), h->at<uint16_t>(L.pb), h->at<uint16_t>(L.pbT));
     hipError_t e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         delete h;
@@ -689,7 +1014,7 @@ int lb_mlp_set_params(lb_mlp *h, const float *host_params)
         hipLaunchKernelGGL(zero_f32_kernel, dim3((kParams + 255) / 256), dim3(256), 0, h->stream,
                            h->at<float>(off), (int64_t)kParams);
     hipLaunchKernelGGL(mirror_kernel, dim3((kParams + 255) / 256), dim3(256), 0, h->stream,
-                       h->at<float>(h->L.p), h->at<uint16_t>(h->L.pb), kParams);
+                       h->at<float>(h->L.p), h->at<uint16_t>(h->L.pb), h->at<uint16_t>(h->L.pbT));
     MLP_TRY(hipGetLastError());
     MLP_TRY(hipStreamSynchronize(h->stream));
     h->step = 0;
@@ -723,7 +1048,7 @@ int lb_mlp_forward_layered(lb_mlp *h, const float *dev_x, int32_t B, float *dev_
     int st = check_batch(h, B);
     if (st) return st;
     if (!dev_x || !dev_y) return lbw_fail_msg(LB_EINVAL, "NULL argument");
-    forward(h, dev_x, B, dev_y);
+    forward(h, dev_x, B, dev_y, nullptr);
     MLP_TRY(hipGetLastError());
     return LB_OK;
 }
@@ -734,8 +1059,9 @@ int lb_mlp_grad(lb_mlp *h, const float *dev_x, const float *dev_t, int32_t B, fl
     int st = check_batch(h, B);
     if (st) return st;
     if (!dev_x || !dev_t || !host_grads) return lbw_fail_msg(LB_EINVAL, "NULL argument");
-    forward(h, dev_x, B, h->at<float>(h->L.y));
-    backward(h, dev_t, B);
+    forward(h, dev_x, B, h->at<float>(h->L.y), dev_t);
+    backward(h, dev_x, B);
+    finish(h, finish_args(h, B));
     MLP_TRY(hipGetLastError());
     MLP_TRY(hipMemcpyAsync(host_grads, h->at<float>(h->L.g), 4 * (size_t)kParams,
                            hipMemcpyDeviceToHost, h->stream));
@@ -752,17 +1078,22 @@ int lb_mlp_train_step(lb_mlp *h, const float *dev_x, const float *dev_t, int32_t
     int st = check_batch(h, B);
     if (st) return st;
     if (!dev_x || !dev_t) return lbw_fail_msg(LB_EINVAL, "NULL argument");
-    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
-        return lbw_fail_msg(LB_EINVAL, "bad Adam hyper-parameters");
-    forward(h, dev_x, B, h->at<float>(h->L.y));
-    backward(h, dev_t, B);
-    h->step++;
-    const float c1 = 1.f - std::pow(beta1, (float)h->step);
-    const float c2 = 1.f - std::pow(beta2, (float)h->step);
-    hipLaunchKernelGGL(adam_kernel, dim3((kParams + 255) / 256), dim3(256), 0, h->stream,
-                       h->at<float>(h->L.p), h->at<float>(h->L.g), h->at<float>(h->L.m),
-                       h->at<float>(h->L.v), h->at<uint16_t>(h->L.pb), kParams, lr, beta1, beta2,
-                       eps, c1, c2);
+    if ((st = check_adam(lr, beta1, beta2, eps))) return st;
+    adam_step(h, dev_x, dev_t, B, lr, beta1, beta2, eps);
+    MLP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
+int lb_mlp_train_steps(lb_mlp *h, const float *dev_x, const float *dev_t, int32_t B,
+                       int32_t n_steps, const float *host_lr, float beta1, float beta2, float eps)
+{
+    int st = check_batch(h, B);
+    if (st) return st;
+    if (!dev_x || !dev_t || n_steps < 0 || (n_steps > 0 && !host_lr))
+        return lbw_fail_msg(LB_EINVAL, "bad argument");
+    for (int s = 0; s < n_steps; ++s)
+        if ((st = check_adam(host_lr[s], beta1, beta2, eps))) return st;
+    for (int s = 0; s < n_steps; ++s) adam_step(h, dev_x, dev_t, B, host_lr[s], beta1, beta2, eps);
     MLP_TRY(hipGetLastError());
     return LB_OK;
 }

@@ -52,6 +52,8 @@ def _mlp_lib():
         L.lb_mlp_grad.argtypes = [vp, vp, vp, C.c_int32, _fp, C.POINTER(C.c_double)]
         L.lb_mlp_train_step.argtypes = [vp, vp, vp, C.c_int32, C.c_float, C.c_float, C.c_float,
                                         C.c_float]
+        L.lb_mlp_train_steps.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, _fp, C.c_float,
+                                         C.c_float, C.c_float]
         L.lb_mlp_last_loss.argtypes = [vp, C.POINTER(C.c_double)]
         L.lb_mlp_mfma_probe.argtypes = [vp, vp, vp, vp]
         L.lb_mlp_activation.argtypes = [vp, C.c_int64, C.c_int32, vp, vp]
@@ -189,25 +191,38 @@ class MLP:
         rng = np.random.Generator(np.random.PCG64(seed))
         L = _mlp_lib()
         losses = []
-        order = rng.permutation(n)
-        pos = 0
-        for s in range(steps):
-            if batch == n:
-                xb, tb = x_d, t_d
-            else:
-                if pos + batch > n:
-                    order, pos = rng.permutation(n), 0
-                idx = torch.as_tensor(order[pos: pos + batch], device="cuda")
-                pos += batch
-                xb, tb = x_d[idx].contiguous(), t_d[idx].contiguous()
-            cur = lr if lr_final is None else lr * (lr_final / lr) ** (s / max(steps - 1, 1))
-            lbwave._check(L.lb_mlp_train_step(self._h, C.c_void_p(xb.data_ptr()),
-                                              C.c_void_p(tb.data_ptr()), len(tb), cur, beta1,
-                                              beta2, eps))
+        sched = np.array([lr if lr_final is None else lr * (lr_final / lr) ** (s / max(steps - 1, 1))
+                          for s in range(steps)], dtype=np.float32)
+
+        def log(s):
             if log_every and (s % log_every == 0 or s == steps - 1):
                 v = C.c_double()
                 lbwave._check(L.lb_mlp_last_loss(self._h, C.byref(v)))
                 losses.append((s, v.value))
+
+        if batch == n:
+            # full batch: the steps between two logged losses go down in one call
+            marks = sorted({0, steps} | ({s + 1 for s in range(0, steps, log_every)} | {steps}
+                                         if log_every else set()))
+            for a, b in zip(marks[:-1], marks[1:]):
+                lbwave._check(L.lb_mlp_train_steps(self._h, C.c_void_p(x_d.data_ptr()),
+                                                   C.c_void_p(t_d.data_ptr()), n, b - a,
+                                                   sched[a:b].ctypes.data_as(_fp), beta1, beta2,
+                                                   eps))
+                log(b - 1)
+            return losses
+        order = rng.permutation(n)
+        pos = 0
+        for s in range(steps):
+            if pos + batch > n:
+                order, pos = rng.permutation(n), 0
+            idx = torch.as_tensor(order[pos: pos + batch], device="cuda")
+            pos += batch
+            xb, tb = x_d[idx].contiguous(), t_d[idx].contiguous()
+            lbwave._check(L.lb_mlp_train_step(self._h, C.c_void_p(xb.data_ptr()),
+                                              C.c_void_p(tb.data_ptr()), len(tb), float(sched[s]),
+                                              beta1, beta2, eps))
+            log(s)
         return losses
 
 
