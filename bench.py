@@ -63,7 +63,17 @@ def parse():
                          "network alone (training, held-out error, inference rate); cylinder: "
                          "the 2D FP64 cylinder, alone and as a batch of positions")
     ap.add_argument("--batch-seed", type=int, default=2404)
-    ap.add_argument("--batch-n", type=int, default=256)
+    ap.add_argument("--batch-n", type=int, default=256,
+                    help="boxes of the uneven batch (--workload batch)")
+    ap.add_argument("--batch-subset", type=int, default=32,
+                    help="boxes of the uneven batch (its first draws) timed in the default run")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven-batch leg of the default run")
+    ap.add_argument("--no-cylinder", action="store_true",
+                    help="skip the 2D cylinder leg of the default run")
+    ap.add_argument("--lb-sample", type=int, default=32,
+                    help="draws of the surrogate's training generator run as one batched LB "
+                         "handle in this run, for the surrogate's gain over the batched LB")
     ap.add_argument("--graph", type=int, default=64,
                     help="replay steady steps as captured HIP graphs of this many steps (0 = off)")
     ap.add_argument("--kernel-only", action="store_true",
@@ -147,8 +157,24 @@ def cpu_baseline(x_mid, k, n_steps):
                       f"256x128x128 lattice with surface measurement ({dt:.1f} s)"}
 
 
-def surrogate_leg(stream, batch, steps=8000):
-    """Train the surrogate on the LB data, score it held out, time its fused inference."""
+def lb_sample_rate(n, graph):
+    """Forces/s of the batched LB on the first n draws of the surrogate's training generator
+    (seed 2405, k R <= 0.6), run to completion in one handle in this run.  The forces must
+    equal the stored training forces of the same draws bit for bit."""
+    from paper_2404_02346_amd import surrogate as S
+    d = S.generate(2405, n, verbose=False)
+    stored = json.load(open(os.path.join(SURROGATE_DATA, SURROGATE_TRAIN[0])))["rows"][:n]
+    same = all(a["F"] == b["F"] for a, b in zip(d["rows"], stored))
+    return {"forces_per_s": round(n / d["lb_seconds"], 3), "boxes": n,
+            "seconds": round(d["lb_seconds"], 2), "updates": d["lb_updates"],
+            "forces_equal_stored_training_data": bool(same),
+            "boxes_by_edge": {str(e): sum(1 for r in d["rows"] if r["edge"] == e)
+                              for e in (64, 96, 128, 192)}}
+
+
+def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64):
+    """Train the surrogate on the LB data, score it held out, time its fused inference, and
+    time the batched LB on a sample of the same generator for the comparison."""
     import torch
     from paper_2404_02346_amd import surrogate as S
     files = [os.path.join(SURROGATE_DATA, f) for f in SURROGATE_TRAIN]
@@ -188,10 +214,9 @@ def surrogate_leg(stream, batch, steps=8000):
     tflops = flop * batch / (ms * 1e-3) / 1e12
     n_lb = sum(t["n"] for t in train_sets)
     lb_s = sum(t["lb_seconds"] for t in train_sets)
-    return {
+    lb_run = lb_sample_rate(lb_sample, graph) if lb_sample > 0 else None
+    out = {
         "forces_per_s": round(batch / (ms * 1e-3), 1),
-        "batched_lb_forces_per_s_same_boxes": round(n_lb / lb_s, 3),
-        "gain_over_batched_lb": round(batch / (ms * 1e-3) / (n_lb / lb_s), 1),
         "held_out_error": {k: (round(v, 5) if isinstance(v, float) else v)
                            for k, v in err.items()},
         "fallback_fraction": {
@@ -206,19 +231,24 @@ def surrogate_leg(stream, batch, steps=8000):
                       "batch": batch, "ms": round(ms, 4), "flop_per_sample": flop,
                       "tflops": round(tflops, 1),
                       "frac_of_bf16_peak": round(tflops / BF16_PEAK_TFLOPS, 4)},
+        # the training data's own generation time (an earlier run, stored with the data)
+        "training_data_lb_forces_per_s": round(n_lb / lb_s, 3),
     }
+    if lb_run is not None:
+        out["batched_lb_this_run"] = lb_run
+        out["gain_over_batched_lb"] = round(batch / (ms * 1e-3) / lb_run["forces_per_s"], 1)
+    return out
 
 
-def batch_workload(args):
-    """The uneven batch: every instance to its own length in one handle, vs one at a time."""
+def batch_leg(args, n, stream):
+    """The first n boxes of the seeded uneven batch: every box to its own length in one handle,
+    against the same boxes one at a time (measured single-box step time per box edge)."""
     import torch
     import paper_2404_02346_amd as P
     import workloads
     from paper_2404_02346_amd import surrogate as S
-    torch.cuda.set_device(0)
-    stream = torch.cuda.current_stream()
     cal = S.calibrate_edges(workloads.BATCH_EDGES)
-    probs, info = workloads.batch(args.batch_seed, args.batch_n,
+    probs, info = workloads.batch(args.batch_seed, n,
                                   {e: c["x_mid"] for e, c in cal.items()},
                                   {e: c["k"] for e, c in cal.items()}, return_draws=True)
     r = S.run_batch(probs, storage=args.storage, graph=args.graph)
@@ -229,7 +259,7 @@ def batch_workload(args):
         h = P.LBWave([group[0]], storage=args.storage, stream=stream)
         h.autotune(4)
         h.set_graph(args.graph)
-        h.step(10)
+        h.step(2 * args.graph + 10)  # past the first graph capture
         torch.cuda.synchronize()
         n1 = 300
         t0 = time.perf_counter()
@@ -239,41 +269,61 @@ def batch_workload(args):
         h.close()
         per_edge[e] = ms
         plain_s += ms * 1e-3 * sum(int(p["n_steps"]) for p in group)
-    n = len(probs)
+    return {
+        "boxes": len(probs), "seed": args.batch_seed, "updates": r["updates"],
+        "rejected_draws": info["rejected"], "kernel_variant": r["variant"],
+        "boxes_by_edge": {str(e): sum(1 for p in probs if int(p["nx"]) == e)
+                          for e in workloads.BATCH_EDGES},
+        "batched_seconds": round(r["seconds"], 3), "plain_seconds_estimated": round(plain_s, 3),
+        "mlups": round(r["updates"] / r["seconds"] / 1e6, 1),
+        "forces_per_s": {"batched": round(len(probs) / r["seconds"], 3),
+                         "plain_one_at_a_time": round(len(probs) / plain_s, 3),
+                         "batched_over_plain": round(plain_s / r["seconds"], 3)},
+        "plain_ms_per_step_by_edge": {str(k): round(v, 4) for k, v in per_edge.items()},
+        "forces_x": [float(v) for v in r["F"][:, 0]],
+    }
+
+
+def batch_workload(args):
+    """The uneven batch: every instance to its own length in one handle, vs one at a time."""
+    import torch
+    torch.cuda.set_device(0)
+    leg = batch_leg(args, args.batch_n, torch.cuda.current_stream())
+    n = leg["boxes"]
+    steps = max(90 * int(e) for e, c in leg["boxes_by_edge"].items() if c)
     out = {
-        "metric": METRIC, "value": round(r["updates"] / r["seconds"] / 1e6, 1), "unit": "MLUPS",
-        "n_gpus": 1, "steps": max(int(p["n_steps"]) for p in probs), "warmup": 0,
-        "ms_per_step": round(r["seconds"] / max(int(p["n_steps"]) for p in probs) * 1e3, 4),
+        "metric": METRIC, "value": leg["mlups"], "unit": "MLUPS",
+        "n_gpus": 1, "steps": steps, "warmup": 0,
+        "ms_per_step": round(leg["batched_seconds"] / steps * 1e3, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.storage, "data": "synthetic",
         "config": {"workload": f"uneven batch: {n} seeded cubic boxes (seed {args.batch_seed}), "
                                "edge in {64,96,128,192} = lambda, R~U[4,16], c_p/c0~U[0.8,1.5], "
                                "kh~U[0,pi/2], c0=1/3, 30 periods each (last 10 averaged), one "
                                "handle, graph-replayed steps",
-                   "instances": n, "updates": r["updates"], "rejected_draws": info["rejected"],
-                   "kernel_variant": r["variant"], "graph_chunk": args.graph},
-        "forces_per_s": {"batched": round(n / r["seconds"], 3),
-                         "plain_one_at_a_time": round(n / plain_s, 3),
-                         "batched_over_plain": round(plain_s / r["seconds"], 3)},
-        "batched_seconds": round(r["seconds"], 2), "plain_seconds_estimated": round(plain_s, 2),
-        "plain_ms_per_step_by_edge": {str(k): round(v, 4) for k, v in per_edge.items()},
-        "forces_x": [float(v) for v in r["F"][:, 0]],
+                   "instances": n, "updates": leg["updates"],
+                   "rejected_draws": leg["rejected_draws"],
+                   "kernel_variant": leg["kernel_variant"], "graph_chunk": args.graph},
+        "forces_per_s": leg["forces_per_s"],
+        "batched_seconds": leg["batched_seconds"],
+        "plain_seconds_estimated": leg["plain_seconds_estimated"],
+        "plain_ms_per_step_by_edge": leg["plain_ms_per_step_by_edge"],
+        "forces_x": leg["forces_x"],
     }
     print(json.dumps(out), flush=True)
 
 
-def cylinder_workload(args):
+def cylinder_leg(args, with_oracle):
     """The 2D FP64 cylinder (128 x 64 D2Q5, 5120 steps): one box alone, then 64 positions in one
     handle; the single box's force against the oracle's (the oracle runs on the host cores)."""
     import torch
     import paper_2404_02346_amd as P
     import workloads
-    torch.cuda.set_device(0)
     lam, c0 = 128.0, 0.5
     cal = P.cavity_calibrate(128, c0, 2 * math.pi * c0 / lam)
     p = workloads.cylinder_2d(cal["x_mid"], cal["k"])
     n_steps, cells = int(p["n_steps"]), 128 * 64
-    out = {"mode": "cylinder", "dtype": "f64",
+    out = {"dtype": "f64",
            "config": {"workload": "2D cylinder, D2Q5 128x64, lambda=128, c0=0.5, c_p/c0=1.2, R=8, "
                                   "64 surface points, kh=pi/4, 20 periods (5120 steps), average "
                                   "over the last 5"}}
@@ -284,6 +334,7 @@ def cylinder_workload(args):
         h = P.LBWave(probs, storage="f64")
         h.autotune(4)
         h.set_graph(args.graph)
+        h.step(2 * args.graph + 10)  # past the first graph capture
         h.reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -297,7 +348,7 @@ def cylinder_workload(args):
                     "forces_per_s": round(n_inst / dt, 2)}
         if n_inst == 1:
             out["force_x"] = float(F[0, 0])
-    if not args.no_cpu_baseline:
+    if with_oracle:
         import oracle
         t0 = time.perf_counter()
         ref = oracle.run(p, n_steps)
@@ -306,7 +357,14 @@ def cylinder_workload(args):
                                "kind": "oracle", "sample": "the whole 5120-step run",
                                "force_x": float(ref["F_avg"][0]),
                                "gpu_vs_oracle_rel": abs(out["force_x"] / ref["F_avg"][0] - 1)}
-    print(json.dumps(out), flush=True)
+    return out
+
+
+def cylinder_workload(args):
+    import torch
+    torch.cuda.set_device(0)
+    print(json.dumps({"mode": "cylinder", **cylinder_leg(args, not args.no_cpu_baseline)}),
+          flush=True)
 
 
 def main():
@@ -325,7 +383,8 @@ def main():
     if args.workload == "surrogate":
         import torch
         torch.cuda.set_device(0)
-        sur = surrogate_leg(torch.cuda.current_stream(), args.surrogate_batch, args.surrogate_steps)
+        sur = surrogate_leg(torch.cuda.current_stream(), args.surrogate_batch, args.surrogate_steps,
+                            args.lb_sample, args.graph)
         print(json.dumps({"mode": "surrogate", **(sur or {})}), flush=True)
         return
     import torch
@@ -387,6 +446,9 @@ def main():
     spl = variant[3]
     h.set_graph(args.graph)
     h.step(args.warmup)
+    if args.graph > 0 and args.steps > 2 * args.graph:
+        # the replayed step sequence is captured and instantiated before the clock starts
+        h.step(2 * args.graph + 2)
     h.reset()  # the timed steps start the run from rest
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -412,7 +474,7 @@ def main():
     g = P.LBWave(problems(x_mid, k, with_surface=False), storage=args.storage, stream=stream)
     set_variant(g, variant)
     g.set_graph(args.graph)
-    g.step(10)
+    g.step(2 * args.graph + 10)  # past the first graph capture
     n_k = min(max(args.steps // 10, 50), 1000)
     e0.record(stream)
     g.step(n_k)
@@ -449,7 +511,7 @@ def main():
     else:
         one.autotune(4)  # one box alone: its own best variant
     one.set_graph(args.graph)
-    one.step(10)
+    one.step(2 * args.graph + 10)  # past the first graph capture
     torch.cuda.synchronize()
     n1 = 400
     t1 = time.perf_counter()
@@ -508,8 +570,20 @@ def main():
     if full_run:
         out["forces_x"] = [float(v) for v in F[:, 0]]
         out["n_accum"] = int(nacc[0])
+    if not args.no_batch and args.batch_subset > 0:
+        b = batch_leg(args, args.batch_subset, stream)
+        b.pop("forces_x")
+        out["forces_per_s"]["uneven_batch_batched"] = b["forces_per_s"]["batched"]
+        out["forces_per_s"]["uneven_batch_plain"] = b["forces_per_s"]["plain_one_at_a_time"]
+        out["uneven_batch"] = b
+    if not args.no_cylinder:
+        c = cylinder_leg(args, not args.no_cpu_baseline)
+        out["forces_per_s"]["cylinder_2d_single"] = c["single"]["forces_per_s"]
+        out["forces_per_s"]["cylinder_2d_batch_64"] = c["batch_64"]["forces_per_s"]
+        out["cylinder_2d"] = c
     if not args.no_surrogate:
-        sur = surrogate_leg(stream, args.surrogate_batch, args.surrogate_steps)
+        sur = surrogate_leg(stream, args.surrogate_batch, args.surrogate_steps, args.lb_sample,
+                            args.graph)
         if sur is not None:
             out["forces_per_s"]["surrogate"] = sur["forces_per_s"]
             out["surrogate"] = sur

@@ -123,21 +123,39 @@ size_t lb_wave_workspace_bytes(const lb_wave_desc *descs, int32_t n_inst);
  * them on return), lays out the workspace, builds the compact c^2 tables
  * and surface stencils, and zeroes the state (f^new of step -1 = 0) and the
  * accumulators, all on `hip_stream` (hipStream_t, NULL = default stream).
+ * The sound speed of an analytic object is eq. sound_speed_object of Sec.
+ * "Wave-particle interaction and interpolation" (c_p inside, c0 outside: the
+ * printed sign is inverted, see the descriptor); each surface element's
+ * stencil is the 3 x 3 (x 3) nodes of the 3-point kernel of eq.
+ * InterpolatedFields, taken as a tensor product of the printed 1D kernel,
+ * with its weights precomputed.
  * dev_workspace must be 256-byte aligned device memory of workspace_bytes
  * >= lb_wave_workspace_bytes().  On success *out receives the handle. */
 int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspace,
                    size_t workspace_bytes, void *hip_stream, lb_wave **out);
 
 /* Enqueue n_steps steps for every instance (an instance past max_steps is
- * left untouched).  Asynchronous: returns after enqueueing.  Returns LB_ENAN
- * if a previous lb_surface_force() found a non-finite force. */
+ * left untouched).  A step is the scheme of Sec. "Lattice-Boltzmann for
+ * acoustics": moments (eq. MacroscopicFields), BGK collision with tau = 1/2
+ * towards the wave equilibrium with the local c (eqs. LBM-Collision and
+ * feq_waves), the damped bounce-back walls at x = 0 and nx-1 (eq.
+ * bounce-back) and the imposed density rho_a sin(omega t) at x = 1 (eq.
+ * imposingfields) in driven mode, then advection (eq. LBM-Advection); the
+ * force F(t) of each step is measured as lb_surface_force describes.
+ * Asynchronous: returns after enqueueing.  Returns LB_ENAN if a previous
+ * lb_surface_force() found a non-finite force. */
 int lb_wave_step_n(lb_wave *h, int64_t n_steps);
 
 /* Synchronise the stream and return, per instance in the order given to
  * create, the time average of F(t) over the accumulated steps
  * (F_avg: n_inst*3 doubles, required) and the number of accumulated steps
- * (n_accum: n_inst, may be NULL).  LB_EEMPTY if some instance has none
- * (its F_avg is then 0), LB_ENAN if some force was not finite. */
+ * (n_accum: n_inst, may be NULL).  F(t) is the surface integral of eq.
+ * arf_integral_LBM over the surface elements, with rho1 and J1 interpolated
+ * to each element (eq. InterpolatedFields) from the step's fields; the
+ * average over the steps t >= avg_start follows Sec. "Results and
+ * discussion" (the force is evaluated every step and averaged once the wave
+ * has settled).  LB_EEMPTY if some instance has none (its F_avg is then 0),
+ * LB_ENAN if some force was not finite. */
 int lb_surface_force(lb_wave *h, double *F_avg, int64_t *n_accum);
 
 /* Release the handle (NULL-safe).  Does not free the caller's workspace. */
@@ -163,6 +181,16 @@ int lb_wave_set_state(lb_wave *h, int32_t inst, const double *host_fnew);
 
 /* Copy F(t) for t = 0 .. n-1 (n <= trace_steps) of instance `inst` to
  * host (n*3 doubles); synchronises the stream. */
+
+/* rho1 = sum_i f_i (eq. MacroscopicFields) of instance `inst` at n_cells
+ * cells of its current state (f^new of the last step, whose moments equal
+ * the pre-collision ones off the x sheets), FP64, unscaled.  dev_cells:
+ * n_cells int64 cell indices (z ny + y) nx + x in device memory; dev_out:
+ * n_cells doubles in device memory; an index outside the lattice gives NaN.
+ * Asynchronous on the handle's stream (read after the steps enqueued before
+ * it).  LB_EINVAL for a bad instance, n_cells < 0 or a NULL pointer. */
+int lb_wave_probe_rho(lb_wave *h, int32_t inst, const int64_t *dev_cells, int32_t n_cells,
+                      double *dev_out);
 int lb_wave_force_trace(lb_wave *h, int32_t inst, double *host_F, int64_t n);
 
 /* Where the populations live inside the workspace (for zero-copy reads):

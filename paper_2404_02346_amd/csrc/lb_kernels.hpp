@@ -963,6 +963,29 @@ __global__ void point_source_kernel(const InstDev *inst, int n_inst, const int64
     for (int i = 0; i < Q; ++i) dst[at(i, x, y, z)] = T::to_r(out[i]);
 }
 
+// rho1 = sum_i f_i (eq. MacroscopicFields) at listed cells of one state buffer, summed in
+// FP64 in velocity order and divided by the storage scale; a cell index outside
+// 0 .. ncell-1 gives NaN.  Cell c = (z ny + y) nx + x lives at row (z ny + y) of each plane.
+template <typename S>
+__global__ void probe_rho_kernel(const void *buf, int64_t plane, int Q, int nx, int64_t ncell,
+                                 int pitch, const int64_t *cells, int n, double scale, double *out)
+{
+    using T = StoreTraits<S>;
+    using R = typename T::R;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t c = cells[i];
+    if (c < 0 || c >= ncell) {
+        out[i] = __builtin_nan("");
+        return;
+    }
+    const int64_t off = (c / nx) * pitch + c % nx;
+    const R *f = static_cast<const R *>(buf);
+    double s = 0.0;
+    for (int q = 0; q < Q; ++q) s += (double)T::to_c(f[q * plane + off]);
+    out[i] = s / scale;
+}
+
 __global__ void set_step_kernel(int64_t *tp, int64_t v)
 {
     if (blockIdx.x == 0 && threadIdx.x == 0) {

@@ -1278,6 +1278,43 @@ int lb_wave_force_trace(lb_wave *h, int32_t inst, double *host_F, int64_t n)
     return LB_OK;
 }
 
+int lb_wave_probe_rho(lb_wave *h, int32_t inst, const int64_t *dev_cells, int32_t n_cells,
+                      double *dev_out)
+{
+    if (!h) return fail(LB_EINVAL, "handle is NULL");
+    if (inst < 0 || inst >= h->n) return fail(LB_EINVAL, "instance out of range");
+    if (n_cells < 0 || (n_cells > 0 && (!dev_cells || !dev_out)))
+        return fail(LB_EINVAL, "probe: bad arguments");
+    if (n_cells == 0) return LB_OK;
+    const int ii = h->pos[inst];
+    const InstPlan &P = h->lay.p[inst];
+    const lb_wave_desc &d = h->desc[inst];
+    const void *buf = h->ws + P.off_buf[buf_of(steps_of(h, ii))];
+    const int64_t ncell = (int64_t)d.nx * d.ny * (d.dim == 3 ? d.nz : 1);
+    const int Q = 2 * d.dim + 1;
+    const dim3 grid((unsigned)((n_cells + 255) / 256)), blk(256);
+    switch (h->storage) {
+    case LB_F64:
+        hipLaunchKernelGGL(probe_rho_kernel<double>, grid, blk, 0, h->stream, buf, P.plane, Q,
+                           d.nx, ncell, P.pitch, dev_cells, n_cells, h->scale[inst], dev_out);
+        break;
+    case LB_F32:
+        hipLaunchKernelGGL(probe_rho_kernel<float>, grid, blk, 0, h->stream, buf, P.plane, Q,
+                           d.nx, ncell, P.pitch, dev_cells, n_cells, h->scale[inst], dev_out);
+        break;
+    case LB_F16:
+        hipLaunchKernelGGL(probe_rho_kernel<_Float16>, grid, blk, 0, h->stream, buf, P.plane, Q,
+                           d.nx, ncell, P.pitch, dev_cells, n_cells, h->scale[inst], dev_out);
+        break;
+    default:
+        hipLaunchKernelGGL(probe_rho_kernel<bf16>, grid, blk, 0, h->stream, buf, P.plane, Q,
+                           d.nx, ncell, P.pitch, dev_cells, n_cells, h->scale[inst], dev_out);
+        break;
+    }
+    HIP_TRY(hipGetLastError());
+    return LB_OK;
+}
+
 int lb_wave_set_variant(lb_wave *h, int32_t cells_per_lane, int32_t x_mode, int32_t nontemporal)
 {
     if (!h) return fail(LB_EINVAL, "handle is NULL");

@@ -75,6 +75,7 @@ def lib():
         L.lb_wave_set_state.argtypes = [vp, C.c_int32, _dp]
         L.lb_wave_force_trace.argtypes = [vp, C.c_int32, _dp, C.c_int64]
         L.lb_wave_state_view.argtypes = [vp, C.c_int32, C.POINTER(StateView)]
+        L.lb_wave_probe_rho.argtypes = [vp, C.c_int32, vp, C.c_int32, vp]
         L.lb_wave_set_variant.argtypes = [vp, C.c_int32, C.c_int32, C.c_int32]
         L.lb_wave_get_variant.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                           C.POINTER(C.c_int32)]
@@ -245,6 +246,13 @@ class LBWave:
         out = np.zeros(3 * n)
         _check(lib().lb_wave_force_trace(self._h, int(inst), _ptr(out), n))
         return out.reshape(n, 3)
+
+    def probe_rho(self, cells_dev, out_dev, inst: int = 0):
+        """rho1 at the cells (int64 device tensor) into out_dev (float64 device tensor),
+        stream-ordered after the steps enqueued so far (lb_wave_probe_rho)."""
+        assert cells_dev.dtype.itemsize == 8 and out_dev.numel() >= cells_dev.numel()
+        _check(lib().lb_wave_probe_rho(self._h, int(inst), C.c_void_p(cells_dev.data_ptr()),
+                                       int(cells_dev.numel()), C.c_void_p(out_dev.data_ptr())))
 
     def state_view(self, inst: int = 0) -> StateView:
         v = StateView()

@@ -48,17 +48,38 @@ PAPER_PSI_R2 = {2: 0.999, 3: 0.994}
 
 def problem(dim: int, cal: dict, lam: int, R: float = R_DEF, c0: float = C0,
             cp: float | None = None, rho_a: float = 1.0, kh: float = KH,
-            n_periods: int = 30, avg_periods: int = 10):
-    """One driven box of length lambda with the object at phase kh from the central antinode."""
+            n_periods: int = 30, avg_periods: int = 10, ny: int = 64):
+    """One driven box of length lambda (ny wide) with the object at phase kh from the central
+    antinode."""
     import workloads
     cp = CP_RATIO * c0 if cp is None else cp
-    nx, ny = int(lam), 64
+    nx = int(lam)
     center = (cal["x_mid"] + kh / cal["k"], ny / 2.0, ny / 2.0 if dim == 3 else 0.0)
     n_surf = 2048 if dim == 3 else 64
     p = workloads._problem(dim, nx, ny, ny if dim == 3 else 1, c0, cp, R, center, float(lam),
                            n_periods, avg_periods, n_surf, rho_a=rho_a, kh=kh)
     p["Pa"] = c0 * c0 * cal["A"] * rho_a
     return p
+
+
+# reduced-size members of the sweeps (boxes lambda x 32 (x 32), base lambda = 64), one per swept
+# parameter, small enough for the FP64 oracle to run each in seconds
+REDUCED = {"lam": 64, "ny": 32, "Pa": 2.0, "R": 3.0, "k_lam": 48, "Psi": 4.0}
+
+
+def reduced_points(dim: int, cal_for):
+    """[(name, problem)]: the default set-up at lambda = 64 with one parameter moved as its sweep
+    moves it (amplitude rho_a = 2, radius R = 3, lambda = 48, Psi = 4 at c0 = 0.25)."""
+    r = REDUCED
+    base = cal_for(r["lam"], C0)
+    cp_psi = 1.0 / math.sqrt(1.0 / PSI_C0 ** 2 - r["Psi"])
+    return [
+        ("Pa", problem(dim, base, r["lam"], rho_a=r["Pa"], ny=r["ny"])),
+        ("R", problem(dim, base, r["lam"], R=r["R"], ny=r["ny"])),
+        ("k", problem(dim, cal_for(r["k_lam"], C0), r["k_lam"], ny=r["ny"])),
+        ("Psi", problem(dim, cal_for(r["lam"], PSI_C0), r["lam"], c0=PSI_C0, cp=cp_psi,
+                        ny=r["ny"])),
+    ]
 
 
 def psi(c0: float, cp: float) -> float:

@@ -102,27 +102,19 @@ def spherical_amplitude(p: dict, rho_tr: np.ndarray, t0: int):
 
 
 def rho_probe_gpu(p: dict, cells, t0: int, n: int, storage: str = "f64") -> np.ndarray:
-    """rho1 of steps t0 .. t0+n-1 at the given cells (GPU library), read from the workspace."""
+    """rho1 of steps t0 .. t0+n-1 at the given cells, summed by the GPU library
+    (lb_wave_probe_rho) after each step."""
     import torch
-    cells = np.asarray(cells, dtype=np.int64)
+    cells = torch.as_tensor(np.asarray(cells, dtype=np.int64), device="cuda")
     h = lbwave.LBWave([p], storage=storage)
-    v = h.state_view(0)
-    dt = {"f64": torch.float64, "f32": torch.float32, "f16": torch.float16,
-          "bf16": torch.bfloat16}[storage]
-    nx, ny = p["nx"], p["ny"]
-    x, r = cells % nx, cells // nx
-    idx = torch.as_tensor((r * v.pitch + x), device=h.ws.device)  # row = z * ny + y
-    Q = 2 * p["dim"] + 1
-    out = np.empty((n, cells.size))
+    out = torch.empty((n, cells.numel()), dtype=torch.float64, device="cuda")
     h.step(t0)
     for j in range(n):
         h.step(1)
-        v = h.state_view(0)
-        raw = h.ws[v.offset_bytes: v.offset_bytes + Q * v.plane_bytes].view(dt)
-        planes = raw.reshape(Q, -1)
-        out[j] = (planes[:, idx].double().sum(dim=0) / v.scale).cpu().numpy()
+        h.probe_rho(cells, out[j])
+    res = out.cpu().numpy()
     h.close()
-    return out
+    return res
 
 
 def point_source(storage: str = "f32", r_fit: float | None = None, directions=((1, 0, 0),),
@@ -213,15 +205,9 @@ def coefficients(p: dict, rho_xt: np.ndarray, t0: int):
 
 
 def rho_window_gpu(p: dict, t0: int, n: int, storage: str = "f64"):
-    """rho1(t, x), t = t0 .. t0+n-1: the sum of the post-collision populations of step t (GPU library)."""
-    h = lbwave.LBWave([p], storage=storage)
-    h.step(t0)
-    out = np.empty((n, p["nx"]))
-    for j in range(n):
-        h.step(1)
-        out[j] = h.get_state(0).sum(axis=1)
-    h.close()
-    return out
+    """rho1(t, x), t = t0 .. t0+n-1, of the one-row box: the sum of the populations of step t
+    at every cell, summed by the GPU library (lb_wave_probe_rho)."""
+    return rho_probe_gpu(p, np.arange(p["nx"] * p["ny"] * p.get("nz", 1)), t0, n, storage)
 
 
 def plane_interface(storage: str = "f64", **kw):

@@ -30,7 +30,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 GOLD = os.path.join(HERE, "golden", "sphere3d_oracle_forces.json")
 
 BOUND = {
-    "full": {"f32": 1e-5, "f16": 2e-3, "bf16": 3e-2},
+    # full-size sphere: |dF| / max_j |F_j| at every position, |dF| / |F| where |F| >= max / 5
+    "full_scale": {"f32": 1e-5, "f16": 1e-3, "bf16": 3e-2},
+    "full_rel": {"f32": 1e-2, "f16": 2e-3, "bf16": 5e-2},
     "reduced": {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2},
     "cylinder": {"f64": 1e-12, "f32": 1e-6, "f16": 2e-3, "bf16": 2e-2},
 }
@@ -60,21 +62,43 @@ def run(P, p, storage, spl=1):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
-def test_full_size_sphere_against_oracle_goldens(P, storage):
-    # The 3D workload at full size (256 x 128 x 128, 15360 steps) against the
-    # FP64 oracle's forces written by tests/golden/make_sphere_goldens.py.
+def test_sixteen_positions_against_oracle_goldens(P, storage):
+    # The 3D workload at full size (256 x 128 x 128, 15360 steps), all 16 positions kh_j in one
+    # handle with two steps per launch and graph replay (the benchmark's configuration), against
+    # the FP64 oracle's forces written by tests/golden/make_sphere_goldens.py.  Per position:
+    # |dF_x| / max_j |F_x| (bounded everywhere) and |dF_x| / |F_x| (bounded where |F_x| is at
+    # least a fifth of the largest: near kh = 0 and pi/2 the force crosses zero).
     if not os.path.exists(GOLD):
         pytest.skip("no oracle goldens")
     g = json.load(open(GOLD))
-    for j, rec in sorted(g["positions"].items()):
-        p = workloads.sphere_3d(g["x_mid"], g["k"], rec["kh"])
-        np.testing.assert_allclose(p["center"], rec["center"], atol=1e-12)
-        F = run(P, p, storage, spl=2)  # two steps per launch, as the benchmark runs it
-        e = abs(F[0] - rec["F_avg"][0]) / abs(rec["F_avg"][0])
-        say(f"kh_{j} {storage}: F_x {F[0]:.8e} oracle {rec['F_avg'][0]:.8e} rel {e:.2e}")
-        assert e <= BOUND["full"][storage]
-        if storage == "f32":
-            assert e <= 0.01  # the target: within 1% of the FP64 oracle
+    khs = workloads.sphere_3d_positions(16)
+    probs = [workloads.sphere_3d(g["x_mid"], g["k"], kh) for kh in khs]
+    h = P.LBWave(probs, storage=storage)
+    h.set_steps_per_launch(2)
+    h.set_graph(64)
+    h.step(probs[0]["n_steps"])
+    F, nacc = h.force()
+    h.close()
+    assert np.all(nacc == probs[0]["n_steps"] - probs[0]["avg_start"])
+    gold = {int(j): rec for j, rec in g["positions"].items()}
+    scale = max(abs(rec["F_avg"][0]) for rec in gold.values())
+    for j in sorted(gold):
+        rec = gold[j]
+        np.testing.assert_allclose(probs[j]["center"], rec["center"], atol=1e-12)
+        ref = rec["F_avg"][0]
+        d = abs(F[j, 0] - ref)
+        say(f"kh_{j} {storage}: F_x {F[j, 0]:.8e} oracle {ref:.8e} "
+            f"|dF|/max|F| {d / scale:.2e} rel {d / abs(ref):.2e}")
+        assert d / scale <= BOUND["full_scale"][storage]
+        if abs(ref) >= 0.2 * scale:
+            assert d / abs(ref) <= BOUND["full_rel"][storage]
+    if storage == "f32":
+        # the shape the paper reports: sin 2kh, largest near kh = pi/4, zero at the node
+        fx = F[:, 0]
+        say("F_x by position", np.array2string(fx, precision=4))
+        assert np.argmax(fx) in (6, 7, 8)
+        assert abs(fx[15]) < 0.05 * fx.max()
+        assert np.all(fx[1:15] > 0)
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
@@ -99,33 +123,6 @@ def test_cylinder_all_storages(P, orc):
         e = abs(F[0] - ref) / abs(ref)
         say(f"cylinder {storage}: rel {e:.2e}")
         assert e <= BOUND["cylinder"][storage]
-
-
-def test_sixteen_positions_batched(P):
-    # The benchmark's configuration: all 16 positions in one handle, FP32,
-    # two steps per launch, graph replay of 64-step chunks.
-    # Checks the golden positions and the shape the paper reports
-    # (sin 2kh: largest near kh = pi/4, vanishing at the node kh = pi/2).
-    if not os.path.exists(GOLD):
-        pytest.skip("no oracle goldens")
-    g = json.load(open(GOLD))
-    khs = workloads.sphere_3d_positions(16)
-    probs = [workloads.sphere_3d(g["x_mid"], g["k"], kh) for kh in khs]
-    h = P.LBWave(probs, storage="f32")
-    h.set_steps_per_launch(2)
-    h.set_graph(64)
-    h.step(probs[0]["n_steps"])
-    F, nacc = h.force()
-    h.close()
-    for j, rec in g["positions"].items():
-        e = abs(F[int(j), 0] - rec["F_avg"][0]) / abs(rec["F_avg"][0])
-        say(f"batched kh_{j}: rel {e:.2e}")
-        assert e <= BOUND["full"]["f32"]
-    fx = F[:, 0]
-    say("F_x by position", np.array2string(fx, precision=4))
-    assert np.argmax(fx) in (6, 7, 8)
-    assert abs(fx[15]) < 0.05 * fx.max()
-    assert np.all(fx[1:15] > 0)
 
 
 def test_batch_instances_against_oracle_goldens(P):

@@ -61,7 +61,7 @@ def small_peanut():
 
 @pytest.mark.parametrize("shape", ["ellipsoid", "peanut"])
 @pytest.mark.parametrize("storage,spl,tol", [("f64", 1, 1e-12), ("f64", 2, 1e-12),
-                                             ("f32", 1, 2e-5), ("f32", 2, 2e-5)])
+                                             ("f32", 1, 1e-5), ("f32", 2, 1e-5)])
 def test_ellipsoid_parity(P, orc, shape, storage, spl, tol):
     p = small_ellipsoid() if shape == "ellipsoid" else small_peanut()
     n = 20

@@ -8,7 +8,16 @@ exponent is exactly 2 (the model is linear, the force quadratic); the R and
 k exponents within 15% and 20% of the small-object laws (the paper measured
 3.08 / 2.01 for R and 0.92 / 0.96 for k, attributing the gap to finite kR);
 the force is linear in Psi with R^2 >= 0.99 (paper: 0.994 / 0.999).
+
+One reduced-size member of each sweep (lambda = 64 boxes 32 cells wide; amplitude, radius,
+wavelength and contrast each moved as their sweep moves them) also runs through the FP64 oracle
+on the same problem, and the GPU's FP32 time-averaged force must match it within 1e-4
+(relative), a bound derived from FP32 rounding: the field error after thousands of steps is
+about 1e-6 of its scale and the force is quadratic in the fields.
 """
+import math
+
+import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -43,3 +52,30 @@ def test_power_laws_and_contrast(SW, dim):
     assert abs(res["k"]["exponent"] - 1.0) < 0.2
     assert res["Pa"]["r2"] > 0.999999 and res["R"]["r2"] > 0.98 and res["k"]["r2"] > 0.98
     assert res["Psi"]["r2"] >= 0.99 and res["Psi"]["slope"] > 0
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_reduced_sweep_points_match_oracle(SW, dim):
+    import oracle
+    from paper_2404_02346_amd import lbwave
+    cache = {}
+
+    def cal_for(lam, c0):
+        key = (int(lam), float(c0))
+        if key not in cache:
+            cache[key] = lbwave.cavity_calibrate(int(lam), c0, 2 * math.pi * c0 / lam)
+        return cache[key]
+
+    pts = SW.reduced_points(dim, cal_for)
+    h = lbwave.LBWave([p for _, p in pts], storage="f32", freeze_at_n_steps=True)
+    h.set_graph(64)
+    h.step(max(int(p["n_steps"]) for _, p in pts))
+    F, nacc = h.force()
+    h.close()
+    for (name, p), Fg, na in zip(pts, F, nacc):
+        ref = oracle.run(p, p["n_steps"])
+        e = abs(Fg[0] - ref["F_avg"][0]) / abs(ref["F_avg"][0])
+        say(f"  dim {dim} {name}: GPU {Fg[0]:.9e} oracle {ref['F_avg'][0]:.9e} rel {e:.2e}")
+        assert na == ref["n_acc"]
+        assert e < 1e-4
+        assert np.abs(Fg[1:] - ref["F_avg"][1:]).max() < 1e-4 * abs(ref["F_avg"][0])
