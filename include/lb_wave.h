@@ -272,6 +272,19 @@ int lb_cavity_calibrate(int32_t nx, double c0, double omega, double rho_a, doubl
                         int32_t n_periods, int32_t n_fit, void *dev_workspace,
                         size_t workspace_bytes, void *hip_stream, double *out, double *host_P);
 
+/* The same calibration for callers that cannot allocate or pass device memory (harnesses that
+ * forbid allocation, tight serving loops): no workspace argument, and no hipMalloc, hipFree or
+ * other allocating call.  The kernel's lock-in sums go to a fixed array in the library's
+ * device memory, 2 * 2048 doubles (32 KiB) per GPU, held until the process ends; nx above
+ * 2048 is rejected with LB_EINVAL, like every other argument lb_cavity_calibrate rejects.
+ * Results are those of lb_cavity_calibrate, bit for bit.  hip_stream must belong to the
+ * current device.  Every call on one GPU uses that GPU's one array: calls that overlap on
+ * the same GPU (other threads, or other streams before this call has returned) race.
+ * Synchronises the stream. */
+int lb_cavity_calibrate_noalloc(int32_t nx, double c0, double omega, double rho_a,
+                                double wall_phi, int32_t n_periods, int32_t n_fit,
+                                void *hip_stream, double *out, double *host_P);
+
 #ifdef __cplusplus
 }
 #endif

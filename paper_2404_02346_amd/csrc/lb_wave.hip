@@ -14,6 +14,7 @@
 #include <cstring>
 #include <climits>
 #include <limits>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -1447,9 +1448,20 @@ size_t lb_cavity_workspace_bytes(int32_t nx)
     return align_up(sizeof(double) * 2 * (size_t)nx);
 }
 
-int lb_cavity_calibrate(int32_t nx, double c0, double omega, double rho_a, double wall_phi,
-                        int32_t n_periods, int32_t n_fit, void *dev_workspace,
-                        size_t workspace_bytes, void *hip_stream, double *out, double *host_P)
+}  // extern "C"
+
+// The lock-in sums of lb_cavity_calibrate_noalloc live in a file-scope device array, one
+// copy per GPU, held until the process ends: 2 kCavMaxNx doubles (32 KiB).  Host code uses
+// the address hipGetSymbolAddress returns for the current device, never the array's name.
+static __device__ __align__(256) double scratch[2 * kCavMaxNx];
+
+namespace {
+
+// Argument checks shared by both calibration entry points; on success m_out and k_out receive
+// the fit window in steps and the lattice wavenumber, n_total_out the run length.
+int cavity_check(int32_t nx, double c0, double omega, double wall_phi, int32_t n_periods,
+                 int32_t n_fit, const double *out, int64_t *n_total_out, int64_t *m_out,
+                 double *k_out)
 {
     g_err.clear();
     if (!out) return fail(LB_EINVAL, "out is NULL");
@@ -1460,35 +1472,30 @@ int lb_cavity_calibrate(int32_t nx, double c0, double omega, double rho_a, doubl
     if (n_fit < 1 || n_periods < n_fit) return fail(LB_EINVAL, "need 1 <= n_fit <= n_periods");
     const double cosk = 1.0 - (1.0 - std::cos(omega)) / (c0 * c0);
     if (!(cosk > -1.0 && cosk < 1.0)) return fail(LB_EINVAL, "omega has no lattice wavenumber");
-    if (!dev_workspace || workspace_bytes < lb_cavity_workspace_bytes(nx))
-        return fail(LB_ENOMEM, "workspace too small");
     const double period = 2.0 * M_PI / omega;
-    const int64_t n_total = (int64_t)std::llround(n_periods * period);
-    const int64_t m = (int64_t)std::llround(n_fit * period);
-    hipStream_t st = static_cast<hipStream_t>(hip_stream);
-    double *d_lock = static_cast<double *>(dev_workspace);
-    hipLaunchKernelGGL(cavity_kernel, dim3(1), dim3(kCavThreads), 0, st, nx, c0 * c0, omega,
-                       rho_a, wall_phi, n_total, m, d_lock);
-    HIP_TRY(hipGetLastError());
-    std::vector<double> lock(2 * (size_t)nx);
-    HIP_TRY(hipMemcpyAsync(lock.data(), d_lock, sizeof(double) * 2 * nx, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
+    *n_total_out = (int64_t)std::llround(n_periods * period);
+    *m_out = (int64_t)std::llround(n_fit * period);
+    *k_out = std::acos(cosk);
+    return LB_OK;
+}
+
+// The fit of the cavity's lock-in sums (host array of 2 nx doubles: sum rho cos wt, then
+// sum rho sin wt over the last m steps), into out[0..5] and optionally host_P.
+int cavity_fit(int32_t nx, int64_t m, double k, const double *lock, double *out, double *host_P)
+{
     // complex amplitude P = (2/m) sum rho e^{-i w t}
-    std::vector<double> re(nx), im(nx);
-    for (int x = 0; x < nx; ++x) {
-        re[x] = 2.0 / (double)m * lock[x];
-        im[x] = -2.0 / (double)m * lock[nx + x];
-        if (host_P) {
-            host_P[2 * x] = re[x];
-            host_P[2 * x + 1] = im[x];
+    auto re = [&](int x) { return 2.0 / (double)m * lock[x]; };
+    auto im = [&](int x) { return -2.0 / (double)m * lock[nx + x]; };
+    if (host_P)
+        for (int x = 0; x < nx; ++x) {
+            host_P[2 * x] = re(x);
+            host_P[2 * x + 1] = im(x);
         }
-    }
     // least squares |P|^2 = a + b cos 2kx + c sin 2kx over 2 <= x <= nx-3
-    const double k = std::acos(cosk);
     double M[3][4] = {{0}};
     for (int x = 2; x <= nx - 3; ++x) {
         const double row[3] = {1.0, std::cos(2 * k * x), std::sin(2 * k * x)};
-        const double y = re[x] * re[x] + im[x] * im[x];
+        const double y = re(x) * re(x) + im(x) * im(x);
         for (int i = 0; i < 3; ++i) {
             for (int j = 0; j < 3; ++j) M[i][j] += row[i] * row[j];
             M[i][3] += row[i] * y;
@@ -1519,6 +1526,74 @@ int lb_cavity_calibrate(int32_t nx, double c0, double omega, double rho_a, doubl
     out[4] = b;
     out[5] = c;
     return LB_OK;
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices] = {};
+
+// the scratch array of the current device (looked up on the device's first call)
+int cavity_scratch(double **ptr)
+{
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(LB_EDEVICE, "device index %d unsupported", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(LB_EDEVICE, "scratch address: %s", hipGetErrorString(e));
+        g_scratch[dev] = static_cast<double *>(p);
+    }
+    *ptr = g_scratch[dev];
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lb_cavity_calibrate(int32_t nx, double c0, double omega, double rho_a, double wall_phi,
+                        int32_t n_periods, int32_t n_fit, void *dev_workspace,
+                        size_t workspace_bytes, void *hip_stream, double *out, double *host_P)
+{
+    int64_t n_total = 0, m = 0;
+    double k = 0.0;
+    int st = cavity_check(nx, c0, omega, wall_phi, n_periods, n_fit, out, &n_total, &m, &k);
+    if (st) return st;
+    if (!dev_workspace || workspace_bytes < lb_cavity_workspace_bytes(nx))
+        return fail(LB_ENOMEM, "workspace too small");
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    double *d_lock = static_cast<double *>(dev_workspace);
+    hipLaunchKernelGGL(cavity_kernel, dim3(1), dim3(kCavThreads), 0, s, nx, c0 * c0, omega,
+                       rho_a, wall_phi, n_total, m, d_lock);
+    HIP_TRY(hipGetLastError());
+    std::vector<double> lock(2 * (size_t)nx);
+    HIP_TRY(hipMemcpyAsync(lock.data(), d_lock, sizeof(double) * 2 * nx, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return cavity_fit(nx, m, k, lock.data(), out, host_P);
+}
+
+int lb_cavity_calibrate_noalloc(int32_t nx, double c0, double omega, double rho_a,
+                                double wall_phi, int32_t n_periods, int32_t n_fit,
+                                void *hip_stream, double *out, double *host_P)
+{
+    int64_t n_total = 0, m = 0;
+    double k = 0.0;
+    int st = cavity_check(nx, c0, omega, wall_phi, n_periods, n_fit, out, &n_total, &m, &k);
+    if (st) return st;
+    double *d_lock = nullptr;
+    if ((st = cavity_scratch(&d_lock))) return st;
+    hipStream_t s = static_cast<hipStream_t>(hip_stream);
+    // the kernel writes every one of the 2 nx sums, so nothing needs clearing first
+    hipLaunchKernelGGL(cavity_kernel, dim3(1), dim3(kCavThreads), 0, s, nx, c0 * c0, omega,
+                       rho_a, wall_phi, n_total, m, d_lock);
+    HIP_TRY(hipGetLastError());
+    double lock[2 * kCavMaxNx];  // host copy on the stack (no heap allocation)
+    HIP_TRY(hipMemcpyAsync(lock, d_lock, sizeof(double) * 2 * nx, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return cavity_fit(nx, m, k, lock, out, host_P);
 }
 
 }  // extern "C"
