@@ -71,6 +71,9 @@ def parse():
                     help="skip the uneven-batch leg of the default run")
     ap.add_argument("--no-cylinder", action="store_true",
                     help="skip the 2D cylinder leg of the default run")
+    ap.add_argument("--fallback-sample", type=int, default=4,
+                    help="seeded queries outside the surrogate's box answered by the LB fallback "
+                         "in this run, for the blended forces/s over the whole input box")
     ap.add_argument("--lb-sample", type=int, default=32,
                     help="draws of the surrogate's training generator run as one batched LB "
                          "handle in this run, for the surrogate's gain over the batched LB")
@@ -172,7 +175,26 @@ def lb_sample_rate(n, graph):
                               for e in (64, 96, 128, 192)}}
 
 
-def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64):
+def fallback_rate(net, qkr, qkh, qra, qR, n):
+    """The first n seeded queries outside the trained box, answered by the surrogate's LB
+    fallback (one batched handle, boxes lambda x 64 x 64) in this run: forces/s."""
+    import torch
+    from paper_2404_02346_amd import surrogate as S
+    out = ~S.in_box(qkr, qkh, qra, qR)
+    idx = np.where(out)[0][:n]
+    sur = S.Surrogate(net)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F, used = sur.predict(qkr[idx], qkh[idx], qra[idx], qR[idx])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lam = np.rint(2 * math.pi * qR[idx] / qkr[idx])
+    return {"queries": int(len(idx)), "seconds": round(dt, 2),
+            "forces_per_s": round(len(idx) / dt, 4), "all_used_lb": bool(used.all()),
+            "box_lengths": [int(v) for v in lam], "finite": bool(np.isfinite(F).all())}
+
+
+def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64, fallback_sample=0):
     """Train the surrogate on the LB data, score it held out, time its fused inference, and
     time the batched LB on a sample of the same generator for the comparison."""
     import torch
@@ -196,6 +218,7 @@ def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64):
     qra = qrng.uniform(*S.BOX["ratio"], nq)
     qR = qrng.uniform(4.0, 16.0, nq)
     fallback = float(1.0 - S.in_box(qkr, qkh, qra, qR).mean())
+    fb = fallback_rate(net, qkr, qkh, qra, qR, fallback_sample) if fallback_sample > 0 else None
     x = torch.rand(batch, S.N_IN, device="cuda") * 2 - 1
     y = torch.empty(batch, device="cuda")
     for _ in range(3):
@@ -237,6 +260,13 @@ def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64):
     if lb_run is not None:
         out["batched_lb_this_run"] = lb_run
         out["gain_over_batched_lb"] = round(batch / (ms * 1e-3) / lb_run["forces_per_s"], 1)
+    if fb is not None:
+        # a query stream uniform over the whole input box: the fraction outside the trained box
+        # costs the LB fallback's time per force, the rest the network's
+        nn = batch / (ms * 1e-3)
+        out["fallback_lb_this_run"] = fb
+        out["blended_forces_per_s_whole_box"] = round(
+            1.0 / (fallback / fb["forces_per_s"] + (1.0 - fallback) / nn), 4)
     return out
 
 
@@ -384,7 +414,7 @@ def main():
         import torch
         torch.cuda.set_device(0)
         sur = surrogate_leg(torch.cuda.current_stream(), args.surrogate_batch, args.surrogate_steps,
-                            args.lb_sample, args.graph)
+                            args.lb_sample, args.graph, args.fallback_sample)
         print(json.dumps({"mode": "surrogate", **(sur or {})}), flush=True)
         return
     import torch
@@ -583,7 +613,7 @@ def main():
         out["cylinder_2d"] = c
     if not args.no_surrogate:
         sur = surrogate_leg(stream, args.surrogate_batch, args.surrogate_steps, args.lb_sample,
-                            args.graph)
+                            args.graph, args.fallback_sample)
         if sur is not None:
             out["forces_per_s"]["surrogate"] = sur["forces_per_s"]
             out["surrogate"] = sur

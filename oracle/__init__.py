@@ -74,6 +74,9 @@ def _load():
         lib.orc_run.argtypes = [C.POINTER(_Desc), C.c_int64, _dp, _dp, _dp, _dp, _i64p, _dp,
                                 C.c_int64, C.c_int64, _i64p, C.c_int64, _dp]
         lib.orc_run.restype = C.c_int
+        lib.orc_run_segment.argtypes = [C.POINTER(_Desc), C.c_int64, C.c_int64, _dp, _dp, _dp,
+                                        _i64p]
+        lib.orc_run_segment.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -275,6 +278,29 @@ def run(p: dict, n_steps: int, fnew_init=None, want_fields: bool = False,
     if pr is not None:
         out["rho_probe"] = rp.reshape(ln, pr.size)
     return out
+
+
+def run_segments(p: dict, n_steps: int, n_segments: int, progress=None) -> dict:
+    """``run(p, n_steps)`` in n_segments consecutive pieces (orc_run_segment), carrying the
+    state and the FP64 force sums across them: the same time average, bit for bit, with a
+    progress callback progress(steps_done) after each piece.  Returns F_avg and n_acc."""
+    lib = _load()
+    b = _Bound(p)
+    cur = np.zeros(b.ncell * b.Q)
+    nxt = np.empty_like(cur)
+    acc = np.zeros(3)
+    nacc = C.c_int64(0)
+    bounds = np.linspace(0, int(n_steps), int(n_segments) + 1).round().astype(np.int64)
+    for t0, t1 in zip(bounds[:-1], bounds[1:]):
+        st = lib.orc_run_segment(C.byref(b.desc), int(t0), int(t1 - t0), _ptr(cur), _ptr(nxt),
+                                 _ptr(acc), C.byref(nacc))
+        if st != 0:
+            raise ValueError(f"oracle segment failed with status {st}")
+        cur, nxt = nxt, cur
+        if progress is not None:
+            progress(int(t1))
+    n = nacc.value
+    return {"F_avg": acc / n if n > 0 else np.zeros(3), "n_acc": n}
 
 
 # ---------------------------------------------------------------------------

@@ -284,44 +284,22 @@ static void build_c2(const orc_desc *D, double *c2)
  * steps line_t0 .. line_t0+line_n-1, line_n*nx values), rho_probe (rho1 at
  * the n_probe cell indices probe[] for the same steps, line_n*n_probe values).
  */
-int orc_run(const orc_desc *D, int64_t n_steps, const double *fnew_init, double *fnew_out,
-            double *F_trace, double *F_avg, int64_t *n_acc, double *rho_line, int64_t line_t0,
-            int64_t line_n, const int64_t *probe, int64_t n_probe, double *rho_probe)
+/* The steps t = t0 .. t0 + n_steps - 1 of the loop above on the state *prev (f^new of step
+ * t0 - 1), swapping *prev and *next after each step, adding F(t) for t >= avg_start to acc and
+ * nacc, and recording the optional outputs of orc_run (trace index t - t0). */
+static int run_steps(const orc_desc *D, int64_t t0, int64_t n_steps, double **prev_io,
+                     double **next_io, const double *c2, double *rho, double *J, double *rhoI,
+                     double *JI, double acc[3], int64_t *nacc, double *F_trace, double *rho_line,
+                     int64_t line_t0, int64_t line_n, const int64_t *probe, int64_t n_probe,
+                     double *rho_probe)
 {
     const int dim = D->dim, Q = 2 * dim + 1;
-    if (dim != 2 && dim != 3) return ORC_EINVAL;
-    if (D->nx < 1 || D->ny < 1 || D->nz < 1 || (dim == 2 && D->nz != 1)) return ORC_EINVAL;
-    if (D->xbc == ORC_XBC_DRIVEN && D->nx < 3) return ORC_EINVAL;
-    const int64_t ncell = (int64_t)D->nx * D->ny * D->nz;
     const int driven = (D->xbc == ORC_XBC_DRIVEN);
     const int point = (D->src_kind == 1);
-    if (D->src_kind != 0 && D->src_kind != 1) return ORC_EINVAL;
-    if (point && (driven || D->src_cell[0] < 0 || D->src_cell[0] >= D->nx || D->src_cell[1] < 0 ||
-                  D->src_cell[1] >= D->ny || D->src_cell[2] < 0 || D->src_cell[2] >= D->nz))
-        return ORC_EINVAL;
-    for (int64_t j = 0; j < n_probe; ++j)
-        if (probe[j] < 0 || probe[j] >= ncell) return ORC_EINVAL;
-
-    double *prev = (double *)calloc((size_t)(ncell * Q), sizeof(double));
-    double *next = (double *)malloc(sizeof(double) * (size_t)(ncell * Q));
-    double *c2 = (double *)malloc(sizeof(double) * (size_t)ncell);
-    double *rho = (double *)malloc(sizeof(double) * (size_t)ncell);
-    double *J = (double *)malloc(sizeof(double) * (size_t)(ncell * 3));
-    int n_s = D->n_surf > 0 ? D->n_surf : 1;
-    double *rhoI = (double *)malloc(sizeof(double) * (size_t)n_s);
-    double *JI = (double *)malloc(sizeof(double) * 3 * (size_t)n_s);
-    if (!prev || !next || !c2 || !rho || !J || !rhoI || !JI) {
-        free(prev); free(next); free(c2); free(rho); free(J); free(rhoI); free(JI);
-        return ORC_ENOMEM;
-    }
-    if (fnew_init) memcpy(prev, fnew_init, sizeof(double) * (size_t)(ncell * Q));
-    build_c2(D, c2);
-
-    double acc[3] = {0.0, 0.0, 0.0};
-    int64_t nacc = 0;
+    double *prev = *prev_io, *next = *next_io;
     int status = ORC_OK;
 
-    for (int64_t t = 0; t < n_steps && status == ORC_OK; ++t) {
+    for (int64_t t = t0; t < t0 + n_steps && status == ORC_OK; ++t) {
         const double rho_src = D->rho_a * sin(D->omega * (double)t);
 #pragma omp parallel for schedule(static)
         for (int z = 0; z < D->nz; ++z)
@@ -370,16 +348,66 @@ int orc_run(const orc_desc *D, int64_t n_steps, const double *fnew_init, double 
             double F[3];
             orc_surface_integral(D, rhoI, JI, F);
             if (F_trace)
-                for (int a = 0; a < 3; ++a) F_trace[3 * t + a] = F[a];
+                for (int a = 0; a < 3; ++a) F_trace[3 * (t - t0) + a] = F[a];
             if (t >= D->avg_start) {
                 for (int a = 0; a < 3; ++a) acc[a] += F[a];
-                ++nacc;
+                ++*nacc;
             }
         }
         double *tmp = prev;
         prev = next;
         next = tmp;
     }
+    *prev_io = prev;
+    *next_io = next;
+    return status;
+}
+
+static int check_desc(const orc_desc *D)
+{
+    const int dim = D->dim;
+    if (dim != 2 && dim != 3) return ORC_EINVAL;
+    if (D->nx < 1 || D->ny < 1 || D->nz < 1 || (dim == 2 && D->nz != 1)) return ORC_EINVAL;
+    if (D->xbc == ORC_XBC_DRIVEN && D->nx < 3) return ORC_EINVAL;
+    const int driven = (D->xbc == ORC_XBC_DRIVEN);
+    const int point = (D->src_kind == 1);
+    if (D->src_kind != 0 && D->src_kind != 1) return ORC_EINVAL;
+    if (point && (driven || D->src_cell[0] < 0 || D->src_cell[0] >= D->nx || D->src_cell[1] < 0 ||
+                  D->src_cell[1] >= D->ny || D->src_cell[2] < 0 || D->src_cell[2] >= D->nz))
+        return ORC_EINVAL;
+    return ORC_OK;
+}
+
+int orc_run(const orc_desc *D, int64_t n_steps, const double *fnew_init, double *fnew_out,
+            double *F_trace, double *F_avg, int64_t *n_acc, double *rho_line, int64_t line_t0,
+            int64_t line_n, const int64_t *probe, int64_t n_probe, double *rho_probe)
+{
+    int status = check_desc(D);
+    if (status != ORC_OK) return status;
+    const int Q = 2 * D->dim + 1;
+    const int64_t ncell = (int64_t)D->nx * D->ny * D->nz;
+    for (int64_t j = 0; j < n_probe; ++j)
+        if (probe[j] < 0 || probe[j] >= ncell) return ORC_EINVAL;
+
+    double *prev = (double *)calloc((size_t)(ncell * Q), sizeof(double));
+    double *next = (double *)malloc(sizeof(double) * (size_t)(ncell * Q));
+    double *c2 = (double *)malloc(sizeof(double) * (size_t)ncell);
+    double *rho = (double *)malloc(sizeof(double) * (size_t)ncell);
+    double *J = (double *)malloc(sizeof(double) * (size_t)(ncell * 3));
+    int n_s = D->n_surf > 0 ? D->n_surf : 1;
+    double *rhoI = (double *)malloc(sizeof(double) * (size_t)n_s);
+    double *JI = (double *)malloc(sizeof(double) * 3 * (size_t)n_s);
+    if (!prev || !next || !c2 || !rho || !J || !rhoI || !JI) {
+        free(prev); free(next); free(c2); free(rho); free(J); free(rhoI); free(JI);
+        return ORC_ENOMEM;
+    }
+    if (fnew_init) memcpy(prev, fnew_init, sizeof(double) * (size_t)(ncell * Q));
+    build_c2(D, c2);
+
+    double acc[3] = {0.0, 0.0, 0.0};
+    int64_t nacc = 0;
+    status = run_steps(D, 0, n_steps, &prev, &next, c2, rho, J, rhoI, JI, acc, &nacc, F_trace,
+                       rho_line, line_t0, line_n, probe, n_probe, rho_probe);
 
     if (status == ORC_OK) {
         if (fnew_out) memcpy(fnew_out, prev, sizeof(double) * (size_t)(ncell * Q));
@@ -387,6 +415,40 @@ int orc_run(const orc_desc *D, int64_t n_steps, const double *fnew_init, double 
             for (int a = 0; a < 3; ++a) F_avg[a] = nacc > 0 ? acc[a] / (double)nacc : 0.0;
         if (n_acc) *n_acc = nacc;
     }
+    free(prev); free(next); free(c2); free(rho); free(J); free(rhoI); free(JI);
+    return status;
+}
+
+/* Steps t0 .. t0 + n_steps - 1 of orc_run from the state fnew_init (f^new of step t0 - 1,
+ * required), continuing the FP64 force accumulator: acc (3 sums) and n_acc are read and
+ * written back.  fnew_out (required) receives f^new of the last step.  Running steps 0 .. n-1
+ * as consecutive segments this way gives the same sums, and so the same time average
+ * acc / n_acc, as one orc_run of n steps. */
+int orc_run_segment(const orc_desc *D, int64_t t0, int64_t n_steps, const double *fnew_init,
+                    double *fnew_out, double *acc, int64_t *n_acc)
+{
+    int status = check_desc(D);
+    if (status != ORC_OK) return status;
+    if (!fnew_init || !fnew_out || !acc || !n_acc || t0 < 0 || n_steps < 0) return ORC_EINVAL;
+    const int Q = 2 * D->dim + 1;
+    const int64_t ncell = (int64_t)D->nx * D->ny * D->nz;
+    double *prev = (double *)malloc(sizeof(double) * (size_t)(ncell * Q));
+    double *next = (double *)malloc(sizeof(double) * (size_t)(ncell * Q));
+    double *c2 = (double *)malloc(sizeof(double) * (size_t)ncell);
+    double *rho = (double *)malloc(sizeof(double) * (size_t)ncell);
+    double *J = (double *)malloc(sizeof(double) * (size_t)(ncell * 3));
+    int n_s = D->n_surf > 0 ? D->n_surf : 1;
+    double *rhoI = (double *)malloc(sizeof(double) * (size_t)n_s);
+    double *JI = (double *)malloc(sizeof(double) * 3 * (size_t)n_s);
+    if (!prev || !next || !c2 || !rho || !J || !rhoI || !JI) {
+        free(prev); free(next); free(c2); free(rho); free(J); free(rhoI); free(JI);
+        return ORC_ENOMEM;
+    }
+    memcpy(prev, fnew_init, sizeof(double) * (size_t)(ncell * Q));
+    build_c2(D, c2);
+    status = run_steps(D, t0, n_steps, &prev, &next, c2, rho, J, rhoI, JI, acc, n_acc, NULL,
+                       NULL, 0, 0, NULL, 0, NULL);
+    if (status == ORC_OK) memcpy(fnew_out, prev, sizeof(double) * (size_t)(ncell * Q));
     free(prev); free(next); free(c2); free(rho); free(J); free(rhoI); free(JI);
     return status;
 }

@@ -10,6 +10,8 @@ usage: python -m paper_2404_02346_amd.make_surrogate_data --seed 2405 --n 4096 -
        (samples 0 .. n-1; --start S writes samples S .. n-1 only)
        python -m paper_2404_02346_amd.make_surrogate_data --merge PART... --out FILE
        (joins consecutive ranges of one seed, e.g. runs split to bound their length)
+       python -m paper_2404_02346_amd.make_surrogate_data --channel --seed S --n N --out FILE
+       (small k R in [0.05, 2 pi 4/192): boxes lambda x 64 x 64, workloads.channel_draws)
 """
 import argparse
 import json
@@ -31,6 +33,8 @@ def main():
     ap.add_argument("--kr-max", type=float, default=0.6)
     ap.add_argument("--chunk", type=int, default=256)
     ap.add_argument("--storage", default="f32")
+    ap.add_argument("--channel", action="store_true",
+                    help="small-kR draws in boxes lambda x 64 x 64 instead of the cubic batch")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     from paper_2404_02346_amd import surrogate as S
@@ -47,8 +51,12 @@ def main():
         import torch
         torch.cuda.set_device(0)
         t0 = time.time()
-        data = S.generate(a.seed, a.n, kr_max=a.kr_max, storage=a.storage, chunk=a.chunk,
-                          start=a.start)
+        if a.channel:
+            data = S.generate_channel(a.seed, a.n, storage=a.storage, chunk=min(a.chunk, 32),
+                                      start=a.start)
+        else:
+            data = S.generate(a.seed, a.n, kr_max=a.kr_max, storage=a.storage, chunk=a.chunk,
+                              start=a.start)
         data["wall_seconds"] = time.time() - t0
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     with open(a.out, "w") as fh:

@@ -335,6 +335,41 @@ def generate(seed: int, n: int, cal=None, kr_max: float = 0.6, storage: str = "f
             "lb_updates": upd}
 
 
+def generate_channel(seed: int, n: int, cal=None, storage: str = "f32", chunk: int = 32,
+                     start: int = 0, verbose: bool = True):
+    """Seeded samples start .. n-1 at small k R (workloads.channel_draws: boxes lambda x 64 x 64,
+    k R in [0.05, 2 pi 4/192)) with their LB forces, as generate() does for the cubic boxes."""
+    import workloads
+    draws, rejected = workloads.channel_draws(seed, n)
+    draws = draws[start:]
+    cal = dict(cal or {})
+    missing = sorted({d[0] for d in draws} - set(cal))
+    if missing:
+        cal.update(calibrate_edges(missing))
+    rows, secs, upd = [], 0.0, 0
+    for s in range(0, len(draws), chunk):
+        part = draws[s: s + chunk]
+        probs = [workloads.channel_problem(d, cal[d[0]]["x_mid"], cal[d[0]]["k"]) for d in part]
+        for p in probs:
+            if not workloads.geometry_ok(p):
+                raise ValueError("channel box cannot hold its object")
+        r = run_batch(probs, storage=storage)
+        secs += r["seconds"]
+        upd += r["updates"]
+        if verbose:
+            print(f"channel batch {(start + s) // chunk}: {len(part)} instances, "
+                  f"{r['updates']:.3e} updates in {r['seconds']:.1f} s", flush=True)
+        for p, d, F in zip(probs, part, r["F"]):
+            lam, R = d[0], d[1]
+            F0 = force_scale(R, cal[lam]["Pa"], lam)
+            rows.append({"edge": int(lam), "box": [int(lam), int(p["ny"]), int(p["nz"])],
+                         "R": R, "ratio": d[2], "kh": d[3], "kR": 2 * math.pi * R / lam,
+                         "F": [float(v) for v in F], "F_over_F0": float(F[0] / F0)})
+    return {"seed": seed, "n": n - start, "start": start, "kr_max": 2 * math.pi * 4.0 / 192.0,
+            "storage": storage, "generator": "channel", "rows": rows, "rejected_draws": rejected,
+            "lb_seconds": secs, "lb_updates": upd}
+
+
 def merge(parts):
     """Join consecutive sample ranges of one seed (as written by generate) into one data set."""
     parts = sorted(parts, key=lambda d: d.get("start", 0))
@@ -401,14 +436,19 @@ def error_metric(pred, ref):
 class Surrogate:
     """Trained network with the plain LB as fallback outside the training box.
 
-    A fallback query runs a cubic box of edge = wavelength = 2 pi R / kR
-    cells (rounded, at least min_edge), so that it keeps the requested
-    resolution R as closely as the integer edge allows.
+    A fallback query runs a box of length lambda = 2 pi R / kR cells
+    (rounded, at least min_edge), so that it keeps the requested resolution R
+    as closely as the integer length allows, and of cross-section
+    width x width cells: the paper's L_y = L_z = 64 (Sec. Results and
+    discussion), or the length if that is smaller.  The sphere and its
+    integration surface (radius R + 2, kernel reach 1.5) fit across 64 cells
+    for every R <= 16.
     """
 
-    def __init__(self, mlp: MLP, min_edge: int = 32, cal=None):
+    def __init__(self, mlp: MLP, min_edge: int = 32, width: int = 64, cal=None):
         self.mlp = mlp
         self.min_edge = min_edge
+        self.width = width
         self.cal = dict(cal or {})
 
     def predict(self, kR, kh, ratio, R):
@@ -430,9 +470,13 @@ class Surrogate:
             probs = []
             for i, e in zip(bad, edges):
                 c = self.cal[e]
-                p = workloads.sphere_3d(c["x_mid"], c["k"], float(kh[i]), shape=(e, e, e),
+                w = min(e, self.width)
+                p = workloads.sphere_3d(c["x_mid"], c["k"], float(kh[i]), shape=(e, w, w),
                                         lam=float(e), R=float(kR[i] * e / (2 * math.pi)),
                                         cp_ratio=float(ratio[i]), n_surf=2048, c0=C0)
+                if not workloads.geometry_ok(p):
+                    raise ValueError(f"fallback box {e} x {w} x {w} cannot hold R = "
+                                     f"{p['radius']:.2f} with its integration surface")
                 probs.append(p)
             r = run_batch(probs, autotune=False)
             for j, (i, e) in enumerate(zip(bad, edges)):

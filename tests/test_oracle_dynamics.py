@@ -297,3 +297,16 @@ def test_surface_integral_divergence_theorem_3d(orc):
     J[:, 0] = b * xyz[:, 0]
     F = orc.surface_integral(p, np.zeros(N), J)
     assert F[0] == pytest.approx(-(b ** 2 / rho0) * x0 * V, rel=2e-3)
+
+
+def test_segmented_run_equals_one_run(orc):
+    # a driven 3D box with an object and surface measurement across the averaging start,
+    # split into uneven pieces: the same time-averaged force, bit for bit
+    import workloads
+    cal = orc.cavity_calibration(32, 0.5, 2 * math.pi * 0.5 / 32, n_periods=10)
+    p = workloads.sphere_3d(cal["x_mid"], cal["k"], 0.5, n_periods=3, avg_periods=1,
+                            shape=(32, 16, 16), lam=32.0, R=2.0, n_surf=128)
+    one = orc.run(p, p["n_steps"])
+    seg = orc.run_segments(p, p["n_steps"], 5)
+    assert seg["n_acc"] == one["n_acc"] > 0
+    assert np.array_equal(seg["F_avg"], one["F_avg"])

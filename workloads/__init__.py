@@ -151,6 +151,46 @@ def batch(seed: int, n: int, x_mid_by_edge: dict, k_by_edge: dict, n_periods: in
     return out
 
 
+CHANNEL_WIDTH = 64     # the paper's L_y = L_z = 64 (Sec. Results and discussion)
+
+
+def channel_draws(seed: int, n: int, kr_range=(0.05, 2.0 * math.pi * 4.0 / 192.0),
+                  lam_step: int = 8):
+    """Seeded draws (lambda, R, c_p/c0, kh) for boxes lambda x 64 x 64 at small k R.
+
+    Each draw takes k R ~ U[kr_range), R ~ U[4, 16], c_p/c0 ~ U[0.8, 1.5], kh ~ U[0, pi/2]
+    in that order (numpy PCG64 stream ``seed``); lambda = 2 pi R / k R is rounded to a
+    multiple of lam_step (so that draws share calibrations), and a draw whose k R = 2 pi R /
+    lambda then leaves kr_range is redrawn.  Objects of R <= 16 with their integration
+    surface fit across 64 cells and away from the x sheets for every kh at these lengths.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out, rejected = [], 0
+    while len(out) < n:
+        kr = float(rng.uniform(*kr_range))
+        R = float(rng.uniform(4.0, 16.0))
+        ratio = float(rng.uniform(0.8, 1.5))
+        kh = float(rng.uniform(0.0, math.pi / 2.0))
+        lam = int(lam_step * round(2.0 * math.pi * R / kr / lam_step))
+        kr_eff = 2.0 * math.pi * R / lam
+        if not kr_range[0] <= kr_eff < kr_range[1]:
+            rejected += 1
+            continue
+        out.append((lam, R, ratio, kh))
+    return out, rejected
+
+
+def channel_problem(draw, x_mid: float, k: float, n_periods: int = 30, avg_periods: int = 10,
+                    n_surf: int = 2048, width: int = CHANNEL_WIDTH):
+    """The box lambda x width x width of one channel draw (c0 = 1/3, lambda = the length)."""
+    lam, R, ratio, kh = draw
+    center = (x_mid + kh / k, width / 2.0, width / 2.0)
+    p = _problem(3, int(lam), width, width, BATCH_C0, ratio * BATCH_C0, R, center, float(lam),
+                 n_periods, avg_periods, n_surf, kh=kh)
+    p["cp_ratio"] = ratio
+    return p
+
+
 def random_state(seed: int, ncell: int, Q: int, scale: float = 0.1) -> np.ndarray:
     """Seeded random populations (cells x Q), uniform in [-scale, scale)."""
     rng = np.random.Generator(np.random.PCG64(seed))
