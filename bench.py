@@ -32,9 +32,6 @@ METRIC = ("wave-LB MLUPS & % HBM roofline; forces/s plain vs batched/surrogate a
           "≤2% error")
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0  # dense MFMA
-SURROGATE_DATA = os.path.join(ROOT, "paper_2404_02346_amd", "data")
-SURROGATE_TRAIN = ("lb_forces_seed2405_n4096.json",)
-SURROGATE_TEST = "lb_forces_seed2406_n512.json"
 SHAPE = (256, 128, 128)
 LAM, C0, CP_RATIO, RADIUS, NSURF = 256.0, 0.5, 1.1, 12.0, 2048
 N_POS = 16
@@ -166,7 +163,7 @@ def lb_sample_rate(n, graph):
     equal the stored training forces of the same draws bit for bit."""
     from paper_2404_02346_amd import surrogate as S
     d = S.generate(2405, n, verbose=False)
-    stored = json.load(open(os.path.join(SURROGATE_DATA, SURROGATE_TRAIN[0])))["rows"][:n]
+    stored = S.load_sets(S.TRAIN_FILES[:1])[0]["rows"][:n]
     same = all(a["F"] == b["F"] for a, b in zip(d["rows"], stored))
     return {"forces_per_s": round(n / d["lb_seconds"], 3), "boxes": n,
             "seconds": round(d["lb_seconds"], 2), "updates": d["lb_updates"],
@@ -175,23 +172,27 @@ def lb_sample_rate(n, graph):
                               for e in (64, 96, 128, 192)}}
 
 
-def fallback_rate(net, qkr, qkh, qra, qR, n):
-    """The first n seeded queries outside the trained box, answered by the surrogate's LB
-    fallback (one batched handle, boxes lambda x 64 x 64) in this run: forces/s."""
+def fallback_rate(net, n, seed=2410):
+    """n seeded queries just outside the trained box (c_p/c0 in (1.5, 1.6], the rest uniform over
+    the box), answered by the surrogate's LB fallback in one batched handle (boxes lambda x 64 x
+    64) in this run: forces/s."""
     import torch
     from paper_2404_02346_amd import surrogate as S
-    out = ~S.in_box(qkr, qkh, qra, qR)
-    idx = np.where(out)[0][:n]
+    q = np.random.Generator(np.random.PCG64(seed))
+    kr, kh = q.uniform(*S.BOX["kR"], n), q.uniform(*S.BOX["kh"], n)
+    ra, R = q.uniform(1.5, 1.6, n) + 1e-9, q.uniform(4.0, 16.0, n)
     sur = S.Surrogate(net)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    F, used = sur.predict(qkr[idx], qkh[idx], qra[idx], qR[idx])
+    F, used = sur.predict(kr, kh, ra, R)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    lam = np.rint(2 * math.pi * qR[idx] / qkr[idx])
-    return {"queries": int(len(idx)), "seconds": round(dt, 2),
-            "forces_per_s": round(len(idx) / dt, 4), "all_used_lb": bool(used.all()),
-            "box_lengths": [int(v) for v in lam], "finite": bool(np.isfinite(F).all())}
+    lam = np.rint(2 * math.pi * R / kr)
+    return {"queries": int(n), "seconds": round(dt, 2), "forces_per_s": round(n / dt, 4),
+            "all_used_lb": bool(used.all()), "box_lengths": [int(v) for v in lam],
+            "finite": bool(np.isfinite(F).all()),
+            "sample": f"{n} seeded draws (seed {seed}): c_p/c0 in (1.5, 1.6], kR, kh, R uniform "
+                      "over the box"}
 
 
 def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64, fallback_sample=0):
@@ -199,16 +200,14 @@ def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64, fallback_sa
     time the batched LB on a sample of the same generator for the comparison."""
     import torch
     from paper_2404_02346_amd import surrogate as S
-    files = [os.path.join(SURROGATE_DATA, f) for f in SURROGATE_TRAIN]
-    test = os.path.join(SURROGATE_DATA, SURROGATE_TEST)
-    if not all(os.path.exists(f) for f in files + [test]):
+    if not all(os.path.exists(f) for f in S.data_paths(S.TRAIN_FILES + S.TEST_FILES)):
         return None
-    train_sets = [json.load(open(f)) for f in files]
+    train_sets = S.load_sets(S.TRAIN_FILES)
     if steps > 0:
         net, log, train_s = S.fit(train_sets, steps=steps)
     else:  # untrained network: the inference kernel's speed does not depend on the weights
         net, log, train_s = S.MLP(max_batch=1024, seed=0), [(0, float("nan"))], 0.0
-    te = S.table(json.load(open(test)))
+    te = S.table(*S.load_sets(S.TEST_FILES))
     err = S.error_metric(net.predict(S.normalize(*te[:4])), te[4])
     # share of queries the network hands to the LB: seeded draws over the whole input box
     qrng = np.random.Generator(np.random.PCG64(2407))
@@ -218,7 +217,7 @@ def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64, fallback_sa
     qra = qrng.uniform(*S.BOX["ratio"], nq)
     qR = qrng.uniform(4.0, 16.0, nq)
     fallback = float(1.0 - S.in_box(qkr, qkh, qra, qR).mean())
-    fb = fallback_rate(net, qkr, qkh, qra, qR, fallback_sample) if fallback_sample > 0 else None
+    fb = fallback_rate(net, fallback_sample) if fallback_sample > 0 else None
     x = torch.rand(batch, S.N_IN, device="cuda") * 2 - 1
     y = torch.empty(batch, device="cuda")
     for _ in range(3):
@@ -245,8 +244,8 @@ def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64, fallback_sa
         "fallback_fraction": {
             "value": round(fallback, 4),
             "queries": f"{nq} seeded draws (seed 2407), uniform over kR [0.05, 0.6], kh [0, pi/2], "
-                       "c_p/c0 [0.8, 1.5], R [4, 16] cells; those outside the trained box "
-                       "(kR < 2 pi 4/192) go to the LB"},
+                       "c_p/c0 [0.8, 1.5], R [4, 16] cells; those outside the trained box go to "
+                       "the LB"},
         "test_samples": len(te[0]), "train_samples": n_lb,
         "train_seconds": round(train_s, 2), "train_final_loss": log[-1][1],
         "lb_seconds_for_training_data": round(lb_s, 1),
@@ -266,7 +265,7 @@ def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64, fallback_sa
         nn = batch / (ms * 1e-3)
         out["fallback_lb_this_run"] = fb
         out["blended_forces_per_s_whole_box"] = round(
-            1.0 / (fallback / fb["forces_per_s"] + (1.0 - fallback) / nn), 4)
+            1.0 / (fallback / fb["forces_per_s"] + (1.0 - fallback) / nn), 1)
     return out
 
 

@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import ctypes as C
 import math
+import os
 
 import numpy as np
 
@@ -26,12 +27,33 @@ from . import lbwave
 # input is 1/R with R the radius in cells, R in 4 .. 16
 BOX = {"kR": (0.05, 0.6), "kh": (0.0, math.pi / 2), "ratio": (0.8, 1.5),
        "inv_R": (1.0 / 16.0, 1.0 / 4.0)}
-# where the network is trusted: the batch generator cannot make k R below
-# 2 pi R_min / edge_max = 2 pi 4 / 192, so smaller k R goes to the LB
-TRUST = {"kR": (2 * math.pi * 4.0 / 192.0, 0.6), "kh": BOX["kh"], "ratio": BOX["ratio"],
-         "inv_R": BOX["inv_R"]}
+# where the network is trusted: the whole input box.  The cubic batch generator cannot make k R
+# below 2 pi R_min / edge_max = 2 pi 4 / 192 = 0.131; the training data add draws of k R in
+# [0.05, 0.131) in boxes lambda x 64 x 64 (workloads.channel_draws), so the trained network
+# covers k R from 0.05.  Queries outside the box go to the LB.
+TRUST = {"kR": BOX["kR"], "kh": BOX["kh"], "ratio": BOX["ratio"], "inv_R": BOX["inv_R"]}
 N_IN = 4
 C0 = 1.0 / 3.0  # fluid sound speed of the batched boxes (keeps c_p <= 0.5 < 1/sqrt(3))
+# the LB force data (paper_2404_02346_amd/data): training and held-out sets of both generators
+DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
+TRAIN_FILES = ("lb_forces_seed2405_n4096.json", "lb_forces_channel_seed2408_n704.json")
+TEST_FILES = ("lb_forces_seed2406_n512.json", "lb_forces_channel_seed2409_n88.json")
+
+
+def data_paths(files):
+    """Full paths of data files named in DATA_DIR."""
+    return [os.path.join(DATA_DIR, f) for f in files]
+
+
+def load_sets(files):
+    """The data sets of the given files (names in DATA_DIR)."""
+    import json
+    out = []
+    for f in data_paths(files):
+        with open(f) as fh:
+            out.append(json.load(fh))
+    return out
+
 
 _fp = C.POINTER(C.c_float)
 
@@ -380,7 +402,10 @@ def merge(parts):
             raise ValueError("parts are not consecutive ranges of one seeded data set")
         pos += d["n"]
     rows = [r for d in parts for r in d["rows"]]
-    return {"seed": parts[0]["seed"], "n": len(rows), "start": parts[0].get("start", 0),
+    if any(d.get("generator") != parts[0].get("generator") for d in parts):
+        raise ValueError("parts come from different generators")
+    out = {"generator": parts[0]["generator"]} if "generator" in parts[0] else {}
+    return {**out, "seed": parts[0]["seed"], "n": len(rows), "start": parts[0].get("start", 0),
             "kr_max": parts[0]["kr_max"], "storage": parts[0]["storage"], "rows": rows,
             "rejected_draws": parts[-1]["rejected_draws"],
             "lb_seconds": sum(d["lb_seconds"] for d in parts),

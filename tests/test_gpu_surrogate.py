@@ -18,10 +18,6 @@ import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
-DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
-                    "paper_2404_02346_amd", "data")
-TRAIN = [os.path.join(DATA, "lb_forces_seed2405_n4096.json")]
-TEST = os.path.join(DATA, "lb_forces_seed2406_n512.json")
 
 
 @pytest.fixture(scope="module")
@@ -29,9 +25,9 @@ def S():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    if not all(os.path.exists(f) for f in TRAIN + [TEST]):
-        pytest.skip("no LB force data")
     from paper_2404_02346_amd import surrogate as S
+    if not all(os.path.exists(f) for f in S.data_paths(S.TRAIN_FILES + S.TEST_FILES)):
+        pytest.skip("no LB force data")
     return S
 
 
@@ -41,14 +37,14 @@ def say(*a):
 
 @pytest.fixture(scope="module")
 def trained(S):
-    net, log, secs = S.fit([json.load(open(f)) for f in TRAIN])
+    net, log, secs = S.fit(S.load_sets(S.TRAIN_FILES))
     say(f"trained in {secs:.1f} s, loss {log}")
     yield net
     net.close()
 
 
 def test_held_out_error_and_gain(S, trained):
-    te = S.table(json.load(open(TEST)))
+    te = S.table(*S.load_sets(S.TEST_FILES))
     assert S.in_box(*te[:4]).all()
     pred = trained.predict(S.normalize(*te[:4]))
     err = S.error_metric(pred, te[4])
@@ -61,7 +57,7 @@ def test_held_out_error_and_gain(S, trained):
 
 def test_forces_per_second_gain(S, trained):
     import torch
-    tr = [json.load(open(f)) for f in TRAIN]
+    tr = S.load_sets(S.TRAIN_FILES)
     lb_rate = sum(d["n"] for d in tr) / sum(d["lb_seconds"] for d in tr)  # batched LB forces/s
     x = torch.rand(65536, S.N_IN, device="cuda") * 2 - 1
     y = torch.empty(65536, device="cuda")
