@@ -3,18 +3,24 @@
 FP64 storage is the oracle's arithmetic (parity tests bound it at 1e-10 and
 below).  FP32 storage must stay within 1% of the FP64 oracle on the 3D
 sphere workload (the target); FP16 and BF16 store each population in 16
-bits (FP32 collision, FP64 measurement) and their error is bounded here at
-about ten times what was measured:
+bits (FP32 collision, FP64 measurement).  Measured largest errors, and the
+bound each test sets (the kernels are deterministic: the same inputs give the
+same bits on every run, so a bound a few times the measurement is safe):
 
-  workload                          FP32      FP16      BF16
-  3D sphere, full size, kh_7        9e-8      2e-5      3e-3
-  3D sphere, full size, kh_3        -         4e-4      -
-  3D sphere 64x32x32 (3 positions)  2e-7      7e-4      1.3e-2
-  2D cylinder                       1.2e-7    1.7e-4    2.1e-3
+  workload (error measure)                 FP32           FP16           BF16
+  full-size sphere, 16 positions:
+    |dF| / max_j |F_j|                     1.3e-7 (1e-6)  2.4e-4 (1e-3)  1.4e-2 (3e-2)
+    |dF| / |F|, |F| >= max / 5             1.5e-7 (1e-6)  5.5e-4 (2e-3)  3.4e-2 (5e-2)
+  3D sphere 64x32x32, 3 positions, rel     2.2e-7 (1e-6)  6.8e-4 (3e-3)  1.3e-2 (5e-2)
+  2D cylinder, rel                         1.2e-7 (1e-6)  1.8e-4 (1e-3)  2.2e-3 (1e-2)
+  seed-2404 batch, edges 64-192, rel       3.6e-5 (2e-4)
 
-The time-averaged force is a second-order, time-averaged quantity: the
-rounding noise of the stored populations averages out over the window, which
-is why even BF16 stays at the percent level.
+BF16 misses the 2% target at three full-size positions: 3.4% at kh_2, 2.1%
+at kh_3 and kh_14 (relative to the force there); its error is a smooth
+function of the position (largest at kh_2 .. kh_4), a bias rather than noise.
+FP16 stays within 0.06% everywhere.  The time-averaged force is a
+second-order, time-averaged quantity: the rounding noise of the stored
+populations largely averages out over the window.
 """
 import json
 import math
@@ -31,10 +37,11 @@ GOLD = os.path.join(HERE, "golden", "sphere3d_oracle_forces.json")
 
 BOUND = {
     # full-size sphere: |dF| / max_j |F_j| at every position, |dF| / |F| where |F| >= max / 5
-    "full_scale": {"f32": 1e-5, "f16": 1e-3, "bf16": 3e-2},
-    "full_rel": {"f32": 1e-2, "f16": 2e-3, "bf16": 5e-2},
-    "reduced": {"f32": 1e-5, "f16": 5e-3, "bf16": 5e-2},
-    "cylinder": {"f64": 1e-12, "f32": 1e-6, "f16": 2e-3, "bf16": 2e-2},
+    "full_scale": {"f32": 1e-6, "f16": 1e-3, "bf16": 3e-2},
+    "full_rel": {"f32": 1e-6, "f16": 2e-3, "bf16": 5e-2},
+    "reduced": {"f32": 1e-6, "f16": 3e-3, "bf16": 5e-2},
+    "cylinder": {"f64": 1e-12, "f32": 1e-6, "f16": 1e-3, "bf16": 1e-2},
+    "batch": {"f32": 2e-4},
 }
 
 
@@ -142,8 +149,10 @@ def test_batch_instances_against_oracle_goldens(P):
         assert p["n_steps"] == rec["n_steps"] and p["avg_start"] == rec["avg_start"]
         probs.append(p)
         refs.append(rec["F_avg"])
+    # two steps per launch, so that rows of 96 and 192 cells (two and three wavefronts per row
+    # in the two-step kernel) meet the oracle directly
     h = P.LBWave(probs, storage="f32", freeze_at_n_steps=True)
-    h.autotune(2)
+    h.set_steps_per_launch(2)
     h.set_graph(64)
     h.step(max(p["n_steps"] for p in probs))
     F, nacc = h.force()
@@ -152,4 +161,4 @@ def test_batch_instances_against_oracle_goldens(P):
         e = abs(Fi[0] - ref[0]) / abs(ref[0])
         say(f"edge {p['nx']}: F_x {Fi[0]:.8e} oracle {ref[0]:.8e} rel {e:.2e}")
         assert n == p["n_steps"] - p["avg_start"]
-        assert e <= 1e-3
+        assert e <= BOUND["batch"]["f32"]
