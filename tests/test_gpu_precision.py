@@ -16,9 +16,10 @@ same bits on every run, so a bound a few times the measurement is safe):
   seed-2404 batch, edges 64-192, rel       3.6e-5 (2e-4)
 
 BF16 misses the 2% target at three full-size positions: 3.4% at kh_2, 2.1%
-at kh_3 and kh_14 (relative to the force there); its error is a smooth
-function of the position (largest at kh_2 .. kh_4), a bias rather than noise.
-FP16 stays within 0.06% everywhere.  The time-averaged force is a
+at kh_3 and kh_14 (relative to the force there).  Its force comes out too
+small at 15 of the 16 positions (0.1-1.4% of the largest force), unevenly
+from one position to the next: a systematic loss, not noise.  FP16 stays
+within 0.06% everywhere.  The time-averaged force is a
 second-order, time-averaged quantity: the rounding noise of the stored
 populations largely averages out over the window.
 """
