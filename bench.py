@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true",
                     help="skip training and timing the force surrogate")
     ap.add_argument("--surrogate-batch", type=int, default=1 << 20)
-    ap.add_argument("--surrogate-steps", type=int, default=8000,
+    ap.add_argument("--surrogate-steps", type=int, default=16000,
                     help="Adam steps of the surrogate's training (0: time the untrained network)")
     ap.add_argument("--cpu-steps", type=int, default=800)
     ap.add_argument("--variant", default=None,
@@ -195,7 +195,7 @@ def fallback_rate(net, n, seed=2410):
                       "over the box"}
 
 
-def surrogate_leg(stream, batch, steps=8000, lb_sample=32, graph=64, fallback_sample=0):
+def surrogate_leg(stream, batch, steps=16000, lb_sample=32, graph=64, fallback_sample=0):
     """Train the surrogate on the LB data, score it held out, time its fused inference, and
     time the batched LB on a sample of the same generator for the comparison."""
     import torch

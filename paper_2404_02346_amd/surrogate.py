@@ -419,7 +419,7 @@ def table(*datasets):
                                                                 "F_over_F0"))
 
 
-def fit(train_sets, steps: int = 8000, lr: float = 2e-3, lr_final: float = 3e-5, seed: int = 0,
+def fit(train_sets, steps: int = 16000, lr: float = 2e-3, lr_final: float = 3e-5, seed: int = 0,
         batch: int | None = None, log_every: int = 2000):
     """Train a network on LB data sets with the standard recipe.
 
