@@ -229,11 +229,11 @@ int lb_wave_autotune(lb_wave *h, int32_t n_trial, double *best_ms);
 /* Lattice steps per launch: 1 (step_kernel, the default) or 2 (a fused
  * kernel that advances t -> t + 2 with step t's values held on chip, reading
  * and writing the state about once per two steps).  Two steps per launch
- * need every instance 3D with driven x sheets, nx <= 256 and ny a multiple
- * of the row block, R * 4 / nw rows: nw = pitch / 64 wavefronts cover a
- * row, R = 4 rows per row group (2 for FP64); otherwise LB_EINVAL.
- * Results are
- * bit-identical either way; steps where an instance stops, and odd
+ * need every instance 3D with driven x sheets and ny a multiple of the row
+ * block, R * 4 / nw rows (R = 4 rows per row group for FP32 and 2 for the
+ * other storage types; nw = pitch / 64 wavefronts cover a row up to 256
+ * cells; longer rows run in strips of 254 cells, nw = 4); otherwise
+ * LB_EINVAL.  Results are bit-identical either way; steps where an instance stops, and odd
  * remainders, run one at a time.  lb_wave_autotune also tries two steps per
  * launch when allowed. */
 int lb_wave_set_steps_per_launch(lb_wave *h, int32_t k);

@@ -184,7 +184,7 @@ struct SegInfo {
     int32_t blk0;       // first block of the run (two-step launch)
     int32_t bpi;        // blocks per instance (two-step launch)
     int32_t nyb;        // row blocks per instance (two-step launch)
-    int32_t pad2;
+    int32_t nsx;        // x strips per row (two-step launch; 1: the row fits one block)
 };
 
 // One launch = [reducer blocks][surface blocks][lattice blocks] (the
@@ -481,6 +481,14 @@ __device__ inline void lattice_task(const StepArgs &a, const int64_t t, const in
 // f(t + 1) go to their moment boxes as in lattice_task.
 // ---------------------------------------------------------------------------
 constexpr int kTwoStepMaxPitch = 256;
+// Rows longer than kTwoStepMaxPitch are cut into strips of kStripW owned cells.  A strip's block
+// spans kStripW + 2 lanes: the columns on either side are computed for step t from the loaded
+// state (as the halo rows are) and hand their values inward, so no block waits for another.
+constexpr int kStripW = 4 * 64 - 2;
+__host__ __device__ inline int two_step_strips(int nx, int pitch)
+{
+    return pitch <= kTwoStepMaxPitch ? 1 : (nx + kStripW - 1) / kStripW;
+}
 
 
 template <typename C>
@@ -513,15 +521,17 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
     const SegInfo &sg = a.seg[s];
     const int local = lb - sg.blk0;
     const int il = local / sg.bpi;
+    const int nsx = sg.nsx;
     const int rem = local - il * sg.bpi;
-    const int zc = rem / sg.nyb;
-    const int yb = rem - zc * sg.nyb;
+    const int sx = rem % nsx;  // strips of one row run side by side
+    const int zc = (rem / nsx) / sg.nyb;
+    const int yb = rem / nsx - zc * sg.nyb;
     const auto &I = to_const(a.inst)[sg.first + il];
     const int nx = sg.nx, ny = sg.ny, nz = sg.nz;
     const int pitch = I.pitch;
     const int64_t plane = I.plane;
-    const int nw = pitch / 64;  // wavefronts per row
-    const int ng = 4 / nw;      // row groups per block
+    const int nw = nsx > 1 ? 4 : pitch / 64;  // wavefronts per row (strip)
+    const int ng = 4 / nw;                    // row groups per block
     const int lane = threadIdx.x & 63;
     const int w = wave_uniform(threadIdx.x >> 6);
     const int g = w / nw, xs = w - g * nw;
@@ -529,8 +539,12 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
     const int y0 = (yb * ng + (active ? g : 0)) * R;
     const int z0 = zc * a.zchunk;
     const int zlen = min(a.zchunk, nz - z0);
-    const int x = xs * 64 + lane;
-    const bool xin = active && x < nx;
+    // owned columns [xo, xend); in a strip the first and last lanes are its halo columns
+    const int xo = nsx > 1 ? sx * kStripW : 0;
+    const int xend = nsx > 1 ? min(nx, xo + kStripW) : nx;
+    const int x = (nsx > 1 ? xo - 1 : 0) + xs * 64 + lane;
+    const bool xin = active && x >= 0 && x < nx;  // the lane has a cell
+    const bool own = xin && x >= xo && x < xend;   // ... and advances it to step t + 2
     const C c0sq = (C)I.c0sq;
     const C phi = (C)I.wall_phi;
     const gptr<const C> c2box = to_global<C>(I.c2box);
@@ -670,7 +684,7 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
             C rho = f[0];
 #pragma unroll
             for (int i = 1; i < 7; ++i) rho += f[i];
-            if (meas && own_plane && j >= 0 && j < R && xin)
+            if (meas && own_plane && j >= 0 && j < R && own)
                 store_moments(mom_a, box_rowj(mb_y, mb_z, j), mb_lo[0], mb_n[0], x, rho, f);
             cell_rule<3, C>(f, rho, C2cur[j + 1], x, nx, true, phi, rs_a, o);
 #pragma unroll
@@ -695,7 +709,7 @@ __device__ inline void lattice2_block(const StepArgs &a, const int64_t t, const 
             if (lane == 0) Npx[j] = (active && xs > 0) ? xe[sl][w - 1][j][0] : C(0);
             if (lane == 63) Nmx[j] = (active && xs < nw - 1) ? xe[sl][w + 1][j][1] : C(0);
         }
-        if (p >= 1 && xin) {
+        if (p >= 1 && own) {
             // step t + 1 on plane zq = z0 + p - 1
             const int zq = z0 + p - 1;
             const int mb_zq = box_z(mb_lo, mb_n, zq);

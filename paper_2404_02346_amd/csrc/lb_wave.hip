@@ -1042,9 +1042,11 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
             for (int ii = 0; ii < n_inst; ++ii) {
                 const InstDev &I = h->hinst[ii];
                 int bpi = 0;
-                if (I.xbc == 0 && I.pitch <= kTwoStepMaxPitch) {
-                    const int ng = 4 / (I.pitch / 64);
-                    if (I.ny % (R * ng) == 0) bpi = (I.ny / (R * ng)) * ((I.nz + zc - 1) / zc);
+                if (I.xbc == 0) {
+                    const int nsx = two_step_strips(I.nx, I.pitch);
+                    const int ng = nsx > 1 ? 1 : 4 / (I.pitch / 64);
+                    if (I.ny % (R * ng) == 0)
+                        bpi = (I.ny / (R * ng)) * ((I.nz + zc - 1) / zc) * nsx;
                 }
                 if (bpi == 0) ok = false;
                 total += bpi;
@@ -1079,8 +1081,9 @@ int lb_wave_create(const lb_wave_desc *descs, int32_t n_inst, void *dev_workspac
             sg.tpi = sg.xsegs * I.ny * I.nz;
             sg.blk0 = h->blk0[ii];
             sg.bpi = h->blk0[ii + 1] - h->blk0[ii];
+            sg.nsx = two_step_strips(I.nx, I.pitch);
             if (h->fused_ok) {
-                const int ng = 4 / (I.pitch / 64);
+                const int ng = sg.nsx > 1 ? 1 : 4 / (I.pitch / 64);
                 sg.nyb = I.ny / (two_step_rows(h->storage) * ng);
             }
             h->segs.push_back(sg);
@@ -1135,9 +1138,8 @@ int lb_wave_set_steps_per_launch(lb_wave *h, int32_t k)
     if (!h) return fail(LB_EINVAL, "handle is NULL");
     if (k != 1 && k != 2) return fail(LB_EINVAL, "steps per launch must be 1 or 2");
     if (k == 2 && !h->fused_ok)
-        return fail(LB_EINVAL, "two steps per launch need 3D instances with driven x sheets, "
-                               "nx <= %d and ny a multiple of the row block",
-                    kTwoStepMaxPitch);
+        return fail(LB_EINVAL, "two steps per launch need 3D instances with driven x sheets "
+                               "and ny a multiple of the row block");
     if (k != h->fused) drop_graphs(h);
     h->fused = k;
     return LB_OK;

@@ -2,10 +2,12 @@
 
 The fused kernel must give the same bits as two one-step launches: state,
 per-step force trace and time average, for every storage, for rows of one
-to four wavefronts (nx = 64, 70, 150, 256), z extents that end in a partial
+to four wavefronts (nx = 64, 70, 150, 256), rows longer than 256 cells cut
+into strips of 254 (nx = 257, 300, 520: two, two and three strips, the
+object's surface across a strip boundary), z extents that end in a partial
 plane chunk, several uneven instances in one handle, odd step counts (the
 last step then runs alone), graph replay and instances that stop inside the
-run.  One FP64 case is also compared with the oracle directly.
+run.  FP64 cases are also compared with the oracle directly.
 """
 import numpy as np
 import pytest
@@ -16,6 +18,8 @@ pytestmark = pytest.mark.gpu
 
 # (z, y, x) shapes: nx -> pitch 64/128/192/256 -> 1/2/3/4 wavefronts per row
 SHAPES = [(12, 16, 64), (40, 16, 70), (10, 12, 150), (9, 12, 256)]
+# rows longer than one block: strips of 254 owned cells (the last one partial)
+STRIP_SHAPES = [(8, 16, 257), (6, 16, 300), (5, 16, 520)]
 
 
 @pytest.fixture(scope="module")
@@ -32,10 +36,10 @@ def say(*a):
     print(*a, flush=True)
 
 
-def problem(shape, R=2.0, avg_start=3, max_steps=0, seed=0):
+def problem(shape, R=2.0, avg_start=3, max_steps=0, seed=0, cx=None):
     nz, ny, nx = shape
     c0 = 0.45
-    center = (nx * 0.55, ny / 2.0 + 0.3, nz / 2.0 - 0.2)
+    center = (nx * 0.55 if cx is None else cx, ny / 2.0 + 0.3, nz / 2.0 - 0.2)
     xyz, nrm, area = workloads.fibonacci_surface(center, R + 2.0, 96)
     return {"dim": 3, "nx": nx, "ny": ny, "nz": nz, "xbc": "driven", "c0": c0, "rho0": 1.0,
             "center": center, "radius": R, "cp": 0.55, "d": 4.0, "rho_a": 1.0,
@@ -74,6 +78,15 @@ def test_two_step_is_bitwise_one_step_batched(P, storage):
     one = run(P, probs, storage, 1, 37)
     two = run(P, probs, storage, 2, 37)
     same(one, two)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
+def test_two_step_strips_are_bitwise_one_step(P, storage):
+    # the 520-cell box has its object (and the moment box the surface reads) across the boundary
+    # of its first two strips, x = 254
+    probs = [problem(STRIP_SHAPES[0]), problem(STRIP_SHAPES[1]), problem(STRIP_SHAPES[2], cx=253.6)]
+    say(f"two-step strips vs one-step, {storage}, shapes {STRIP_SHAPES}")
+    same(run(P, probs, storage, 1, 37), run(P, probs, storage, 2, 37))
 
 
 @pytest.mark.parametrize("shape", SHAPES)
@@ -119,8 +132,9 @@ def test_two_step_longest_chunks_with_a_partial_chunk(P):
         assert np.array_equal(x, y)
 
 
-def test_two_step_against_oracle_fp64(P, orc):
-    p = problem((40, 16, 70), avg_start=5)
+@pytest.mark.parametrize("shape,cx", [((40, 16, 70), None), ((10, 16, 300), 254.2)])
+def test_two_step_against_oracle_fp64(P, orc, shape, cx):
+    p = problem(shape, avg_start=5, cx=cx)
     n = 30
     init = workloads.random_state(70, p["nx"] * p["ny"] * p["nz"], 7)
     h = P.LBWave([p], storage="f64", trace_steps=n)
@@ -133,14 +147,14 @@ def test_two_step_against_oracle_fp64(P, orc):
     ref = orc.run(p, n, fnew_init=init, want_fields=True, want_trace=True)
     ef = np.abs(st - ref["fnew"]).max() / np.abs(ref["fnew"]).max()
     et = np.abs(tr - ref["F_trace"]).max() / np.abs(ref["F_trace"]).max()
-    say(f"two-step FP64 vs oracle: field {ef:.2e} trace {et:.2e}")
+    say(f"two-step FP64 vs oracle {shape}: field {ef:.2e} trace {et:.2e}")
     assert ef <= 1e-12 and et <= 1e-11
     assert nacc[0] == ref["n_acc"]
 
 
 def test_two_step_rejected_where_it_does_not_apply(P):
     cases = [problem((6, 10, 70)),            # ny not a multiple of the row block
-             problem((6, 8, 300))]            # row wider than 256 cells
+             problem((6, 10, 300))]           # the same with rows cut into strips
     p2 = dict(problem((6, 16, 64)))
     p2["xbc"] = "periodic"
     for key in ("surf_xyz", "surf_normal", "surf_area"):
