@@ -3,8 +3,9 @@
 The fused kernel must give the same bits as two one-step launches: state,
 per-step force trace and time average, for every storage, for rows of one
 to four wavefronts (nx = 64, 70, 150, 256), rows longer than 256 cells cut
-into strips of 254 (nx = 257, 300, 520: two, two and three strips, the
-object's surface across a strip boundary), z extents that end in a partial
+into strips of 254 cells (nx = 257, 300, 378, 520, 1016: two to four strips,
+the last one partial or full), the object's surface across a strip boundary,
+z extents that end in a partial
 plane chunk, several uneven instances in one handle, odd step counts (the
 last step then runs alone), graph replay and instances that stop inside the
 run.  FP64 cases are also compared with the oracle directly.
@@ -18,8 +19,10 @@ pytestmark = pytest.mark.gpu
 
 # (z, y, x) shapes: nx -> pitch 64/128/192/256 -> 1/2/3/4 wavefronts per row
 SHAPES = [(12, 16, 64), (40, 16, 70), (10, 12, 150), (9, 12, 256)]
-# rows longer than one block: strips of 254 owned cells (the last one partial)
-STRIP_SHAPES = [(8, 16, 257), (6, 16, 300), (5, 16, 520)]
+# rows longer than 256 cells: strips of 254 owned cells, with the object across a strip boundary
+# (x = 254 or 508) in the last three
+STRIP_SHAPES = [((8, 16, 257), None), ((6, 16, 300), None), ((5, 16, 520), 253.6),
+                ((8, 16, 378), 254.3), ((8, 16, 1016), 508.4)]
 
 
 @pytest.fixture(scope="module")
@@ -82,10 +85,8 @@ def test_two_step_is_bitwise_one_step_batched(P, storage):
 
 @pytest.mark.parametrize("storage", ["f32", "f64", "f16", "bf16"])
 def test_two_step_strips_are_bitwise_one_step(P, storage):
-    # the 520-cell box has its object (and the moment box the surface reads) across the boundary
-    # of its first two strips, x = 254
-    probs = [problem(STRIP_SHAPES[0]), problem(STRIP_SHAPES[1]), problem(STRIP_SHAPES[2], cx=253.6)]
-    say(f"two-step strips vs one-step, {storage}, shapes {STRIP_SHAPES}")
+    probs = [problem(shape, cx=cx) for shape, cx in STRIP_SHAPES]
+    say(f"two-step strips vs one-step, {storage}, shapes {[s for s, _ in STRIP_SHAPES]}")
     same(run(P, probs, storage, 1, 37), run(P, probs, storage, 2, 37))
 
 
